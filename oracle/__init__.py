@@ -1,0 +1,182 @@
+"""CPU oracle for the cf4ocl paper's massive PRNG example (Section 5,
+Listings S4 and S5) -- TEST INFRASTRUCTURE.
+
+Only the tests, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package. The GPU library never imports it, and the two
+share no code: this module loads ``liboracle.so`` (built from ``oracle.c``
+with plain gcc) and exposes it with numpy arrays.
+
+The definitions themselves live in ``oracle.c`` (generator and seeding) and
+``profile.py`` (the event-profile arithmetic). This file adds only argument
+marshalling and one plain bookkeeping rule for served requests
+(:func:`serve_expected`).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# The oracle's request record, laid out as in oracle.c.
+REQ_DTYPE = np.dtype([("seed", "<u8"), ("offset", "<u8"), ("length", "<u8"),
+                      ("gid", "<u4"), ("reserved", "<u4")])
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc -O2 (plain C99)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-fPIC",
+                        "-shared", "-o", tmp, _SRC], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        u32, u64, p = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
+        L.oracle_hash_low.argtypes = [u32]
+        L.oracle_hash_low.restype = u32
+        L.oracle_hash_high.argtypes = [u32]
+        L.oracle_hash_high.restype = u32
+        L.oracle_init_state.argtypes = [u64, u32]
+        L.oracle_init_state.restype = u64
+        L.oracle_rng_step.argtypes = [u64]
+        L.oracle_rng_step.restype = u64
+        L.oracle_value.argtypes = [u64, u32, u64]
+        L.oracle_value.restype = u64
+        L.oracle_generate.argtypes = [u64, u32, u64, u32, p]
+        L.oracle_generate.restype = u64
+        L.oracle_generate_u32.argtypes = [u64, u32, u64, u32, p]
+        L.oracle_generate_u32.restype = u64
+        L.oracle_generate_batch.argtypes = [p, u32, p]
+        L.oracle_generate_batch.restype = u64
+        L.oracle_hash_low_range.argtypes = [u32, u64, p]
+        L.oracle_hash_low_range.restype = None
+        L.oracle_hash_high_range.argtypes = [u32, u64, p]
+        L.oracle_hash_high_range.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+# --- scalar definitions -----------------------------------------------------
+
+def hash_low(a: int) -> int:
+    """Listing S4 low-word hash J."""
+    return int(lib().oracle_hash_low(a & 0xFFFFFFFF))
+
+
+def hash_high(a: int) -> int:
+    """Listing S4 high-word hash W."""
+    return int(lib().oracle_hash_high(a & 0xFFFFFFFF))
+
+
+def init_state(seed: int, gid: int) -> int:
+    """Initial state of work-item ``gid`` under ``seed`` (seed 0 = paper)."""
+    return int(lib().oracle_init_state(seed, gid))
+
+
+def rng_step(x: int) -> int:
+    """Listing S5: one (21,35,4) xorshift step."""
+    return int(lib().oracle_rng_step(x))
+
+
+def value(seed: int, gid: int, k: int) -> int:
+    """k-th value of work-item ``gid``'s stream (k sequential steps)."""
+    return int(lib().oracle_value(seed, gid, k))
+
+
+# --- array definitions ------------------------------------------------------
+
+def generate(seed: int, n: int, n_iters: int, cursor: int = 0) -> np.ndarray:
+    """Plain output, iteration-major: out[k, g] = value(seed, g, cursor + k)."""
+    out = np.empty((n_iters, n), dtype=np.uint64)
+    zeros = lib().oracle_generate(seed, n, cursor, n_iters, _ptr(out))
+    if zeros:
+        raise AssertionError("oracle produced %d zero values" % zeros)
+    return out
+
+
+def generate_u32(seed: int, n: int, n_iters: int, cursor: int = 0) -> np.ndarray:
+    """Low 32-bit halves of :func:`generate`."""
+    out = np.empty((n_iters, n), dtype=np.uint32)
+    zeros = lib().oracle_generate_u32(seed, n, cursor, n_iters, _ptr(out))
+    if zeros:
+        raise AssertionError("oracle produced %d zero values" % zeros)
+    return out
+
+
+def make_reqs(seeds, gids, offsets, lengths) -> np.ndarray:
+    m = len(lengths)
+    r = np.zeros(m, dtype=REQ_DTYPE)
+    r["seed"] = np.asarray(seeds, dtype=np.uint64)
+    r["gid"] = np.asarray(gids, dtype=np.uint32)
+    r["offset"] = np.asarray(offsets, dtype=np.uint64)
+    r["length"] = np.asarray(lengths, dtype=np.uint64)
+    return r
+
+
+def generate_batch(reqs: np.ndarray) -> np.ndarray:
+    """Requests packed in order: out[base_j + t] = value(seed_j, gid_j, offset_j + t)."""
+    reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+    total = int(reqs["length"].sum()) if len(reqs) else 0
+    out = np.empty(total, dtype=np.uint64)
+    zeros = lib().oracle_generate_batch(_ptr(reqs), len(reqs), _ptr(out))
+    if zeros:
+        raise AssertionError("oracle produced %d zero values" % zeros)
+    return out
+
+
+def serve_expected(seed: int, submissions) -> list:
+    """Outputs of served requests, given the submission history.
+
+    ``submissions`` is a sequence of (stream_id, length) in submission order.
+    Request r on stream g continues g's stream where the requests submitted
+    to g before r stopped: its first value is value number
+    (sum of the lengths of g's earlier requests). Returns one uint64 array per
+    request, in submission order.
+    """
+    cursor = {}
+    offs = []
+    for g, length in submissions:
+        c = cursor.get(g, 0)
+        offs.append(c)
+        cursor[g] = c + int(length)
+    reqs = make_reqs([seed] * len(offs), [g for g, _ in submissions], offs,
+                     [int(length) for _, length in submissions])
+    flat = generate_batch(reqs)
+    res, base = [], 0
+    for _, length in submissions:
+        res.append(flat[base:base + int(length)])
+        base += int(length)
+    return res
+
+
+def hash_low_range(start: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint32)
+    lib().oracle_hash_low_range(start & 0xFFFFFFFF, count, _ptr(out))
+    return out
+
+
+def hash_high_range(start: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint32)
+    lib().oracle_hash_high_range(start & 0xFFFFFFFF, count, _ptr(out))
+    return out
