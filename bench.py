@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark of the massive-PRNG hot path on one MI355X.
+
+Headline (one JSON line on stdout): the plain generator writing 2^26 streams
+x 256 iterations of uint64 (128 GiB of output per step) into HBM. A step is
+one rngx_generate call over that whole grid (seeding is done once before the
+warm-up). `value` is output GB/s over the timed steps; `roofline` reports the
+generation kernel's own average duration from HIP events recorded on its
+launch stream, against the 8 TB/s HBM3E peak; `cpu_baseline` times the CPU
+oracle on a bounded sample of the same workload.
+
+Run: python bench.py [--steps K] [--warmup W]. Only one GPU is measured.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RNG output GB/s (% HBM peak), batched vs plain; p50/p99 request latency"
+HBM_PEAK_GBS = 8000.0
+GIB = 1 << 30
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_avg_s(stats, name):
+    for agg_name, count, abs_s, _ in stats["agg"]:
+        if agg_name == name:
+            return abs_s / count, count
+    raise RuntimeError("no %s events were profiled" % name)
+
+
+def plain_run(torch, rngx, seed, n, iters, u32, warmup, steps):
+    """Time `steps` generate calls of `iters` iterations over n streams."""
+    rngx.init(seed, n)
+    out = torch.empty(n * iters, dtype=torch.int32 if u32 else torch.int64, device="cuda")
+    gen = rngx.generate_u32 if u32 else rngx.generate
+    for _ in range(warmup):
+        gen(iters, out)
+    torch.cuda.synchronize()
+    rngx.profile_start()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gen(iters, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = rngx.profile_stats()
+    avg, count = kernel_avg_s(st, "RNG_KERNEL")
+    assert count == steps
+    del out
+    torch.cuda.empty_cache()
+    esize = 4 if u32 else 8
+    out_bytes = esize * n * iters
+    return {
+        "wall_s": t1 - t0,
+        "out_gbs": out_bytes * steps / (t1 - t0) / 1e9,
+        "kernel_avg_s": avg,
+        "out_bytes_per_launch": out_bytes,
+        "alg_bytes_per_launch": out_bytes + 16 * n,
+        "kernel_gbs": (out_bytes + 16 * n) / avg / 1e9,
+    }
+
+
+def sweep(torch, rngx, reps):
+    """HBM roofline sweep: n in 2^20..2^26, 256 iterations, seeds 1..4, u64 and u32."""
+    from paper_1609_01257_amd import inputs
+    rows = []
+    for n, seed in zip(inputs.ROOFLINE_N, inputs.ROOFLINE_SEEDS):
+        for u32 in (False, True):
+            r = plain_run(torch, rngx, seed, n, inputs.ROOFLINE_ITERS, u32, 1, reps)
+            rows.append({"n": n, "seed": seed, "dtype": "u32" if u32 else "u64",
+                         "kernel_gbs": round(r["kernel_gbs"], 1),
+                         "out_gbs": round(r["out_gbs"], 1),
+                         "frac_hbm": round(r["kernel_gbs"] / HBM_PEAK_GBS, 4)})
+            log("sweep", rows[-1])
+    return rows
+
+
+def cpu_baseline(n_total, iters):
+    """The CPU oracle, single-threaded, on the first 2^20 work-items of the
+    workload (all iterations)."""
+    import oracle
+    n = 1 << 20
+    t0 = time.perf_counter()
+    out = oracle.generate(1, n, iters)
+    dt = time.perf_counter() - t0
+    gbs = out.nbytes / dt / 1e9
+    del out
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d work-items x %d iterations (u64, %.1f GiB) in %.1f s"
+                      % (n, n_total, iters, n * iters * 8 / GIB, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the size/dtype sweep")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="run only the headline kernel (for profiling)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        log("bench.py measures a single GPU: the generator shards across GPUs with no "
+            "communication, so only --gpus 1 is supported.")
+        sys.exit(2)
+
+    import torch
+    from paper_1609_01257_amd import rngx
+
+    torch.cuda.set_device(0)
+    n, iters, seed = 1 << 26, 256, 1
+    log("headline: plain u64, n=2^26, iters=256, warmup=%d steps=%d" % (args.warmup, args.steps))
+    head = plain_run(torch, rngx, seed, n, iters, False, args.warmup, args.steps)
+    log("headline:", head)
+    result = {
+        "metric": METRIC,
+        "value": round(head["out_gbs"], 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["wall_s"] / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "plain generator, 2^26 streams x 256 iterations of uint64 "
+                               "(128 GiB per step), seed 1, output kept in HBM",
+                   "n_states": n, "iters": iters, "seed": seed,
+                   "launch": rngx.get_launch(False)},
+        "roofline": {"bound": "hbm",
+                     "achieved": round(head["kernel_gbs"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(head["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "kernel": "gen_kernel<u64>",
+                     "kernel_avg_ms": round(head["kernel_avg_s"] * 1e3, 4),
+                     "alg_bytes_per_launch": head["alg_bytes_per_launch"]},
+    }
+    if not args.headline_only:
+        log("u32 headline shape")
+        h32 = plain_run(torch, rngx, seed, n, iters, True, 1, max(3, args.steps // 4))
+        result["u32"] = {"out_gbs": round(h32["out_gbs"], 1),
+                         "kernel_gbs": round(h32["kernel_gbs"], 1),
+                         "frac_hbm": round(h32["kernel_gbs"] / HBM_PEAK_GBS, 4)}
+        if not args.no_sweep:
+            result["sweep"] = sweep(torch, rngx, 3)
+    rngx.shutdown()
+    if not args.no_cpu_baseline and not args.headline_only:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(n, iters)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * rngx.h -- C ABI of an MI355X (gfx950) implementation of the massive
+ * pseudo-random number generator in the example application of "cf4ocl: a C
+ * framework for OpenCL" (Section 5, "Example: massive pseudo-random number
+ * generator"; supplementary Listings S4 and S5).
+ *
+ * What is computed (all arithmetic exact, unsigned, wrapping):
+ *   J(a)  the six-round 32-bit integer hash of Listing S4 ("low bits"),
+ *   W(a)  the five-round shift-multiply hash of Listing S4 ("high bits"),
+ *   H(s, g) = (W(low ^ h) << 32) | low,  low = J(g ^ l),
+ *            l = J(lo32 s) ^ J(0),  h = W(hi32 s) ^ W(0)
+ *         the initial state of work-item g under a 64-bit seed s; s = 0 gives
+ *         exactly the paper's init kernel (low = J(g), high = W(low)); the
+ *         all-zero state, reachable for one (s, g) pair when s != 0, is
+ *         replaced by W(0) << 32,
+ *   XS(x) one step of the 64-bit xorshift of Listing S5: x ^= x << 21;
+ *         x ^= x >> 35; x ^= x << 4,
+ *   V(s, g, k) = XS^k(H(s, g)), value number k of work-item g's stream.
+ * The values written by the init kernel are the first batch of output
+ * (Section 5), so value number 0 of every stream is its initial state.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status (RNGX_OK or a negative RNGX_E_*
+ *    code) unless stated otherwise. On failure, rngx_last_error() returns a
+ *    message for the calling thread (the paper's error-object convention,
+ *    Section 4.1). The library never exits the process.
+ *  - One process-wide generator context, guarded by a mutex; calls from
+ *    several host threads are serialised.
+ *  - Device pointers are plain HIP device addresses on the current device.
+ *    `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *    Work is enqueued asynchronously on `stream`; the library orders its own
+ *    use of the generator state across streams with HIP events.
+ *  - The caller owns every buffer it passes and must keep it alive until the
+ *    enqueued work has completed. The library owns its state buffer, events
+ *    and the text it returns.
+ */
+#ifndef RNGX_H
+#define RNGX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define RNGX_OK 0
+#define RNGX_E_INVAL (-1)  /* invalid argument (NULL, misaligned, 0 states, overflow) */
+#define RNGX_E_NOINIT (-2) /* generator used before rngx_init */
+#define RNGX_E_HIP (-3)    /* HIP runtime error; rngx_last_error() holds its text */
+#define RNGX_E_NOMEM (-4)  /* device allocation failed */
+#define RNGX_E_BUSY (-5)   /* resource temporarily full; retry later */
+
+/* ------------------------------------------------------------------------ */
+/* Generator lifecycle                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Seed n_states streams: state[g] = H(seed, g) for g < n_states (Listing S4;
+ * Section 5, the init kernel). Allocates the library-owned state buffer
+ * (8 * n_states bytes of device memory) on the current device, launches the
+ * init kernel on the library's own stream, resets the cursor to 0 and
+ * restarts the profiler (as the paper starts profiling just before init).
+ * Calling it again releases the previous state first.
+ * Errors: RNGX_E_INVAL if n_states == 0 (n_states is a 32-bit count, as the
+ * paper's nseeds is a cl_uint); RNGX_E_NOMEM; RNGX_E_HIP. */
+int rngx_init(uint64_t seed, uint32_t n_states);
+
+/* Produce the next n_iters iterations of every stream (Section 5: each rng
+ * kernel invocation advances every state once; Eq. 1: 8 * n * i bytes):
+ *     out[k * n_states + g] = V(seed, g, cursor + k),  k < n_iters,
+ * iteration-major, i.e. the byte order the paper's program writes to its
+ * standard output; then cursor += n_iters.
+ * out: device memory of at least 8 * n_states * n_iters bytes, 8-byte
+ *      aligned (16-byte alignment and an even n_states give the fastest
+ *      stores). n_iters == 0 is a successful no-op.
+ * Errors: RNGX_E_NOINIT; RNGX_E_INVAL (out NULL or misaligned, or the byte
+ * count overflows size_t); RNGX_E_HIP. */
+int rngx_generate(uint32_t n_iters, uint64_t *out, void *stream);
+
+/* As rngx_generate, writing the low 32 bits of each value:
+ *     out[k * n_states + g] = (uint32_t)V(seed, g, cursor + k).
+ * It advances the same cursor. out must be 4-byte aligned. */
+int rngx_generate_u32(uint32_t n_iters, uint32_t *out, void *stream);
+
+/* Current generator parameters (any pointer may be NULL).
+ * Errors: RNGX_E_NOINIT. */
+int rngx_info(uint64_t *seed, uint32_t *n_states, uint64_t *cursor);
+
+/* Release the state buffer, events, streams and every other resource the
+ * library holds (the constructor/destructor discipline of Section 4.1).
+ * Safe to call when nothing is initialised. */
+int rngx_shutdown(void);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char *rngx_last_error(void);
+
+/* Static name of a status code (the paper's errors module, Section 4.4). */
+const char *rngx_strerror(int code);
+
+/* ------------------------------------------------------------------------ */
+/* Launch configuration of the plain generator                               */
+/* ------------------------------------------------------------------------ */
+
+/* block: threads per block (64..1024, a multiple of 64).
+ * chunks: 16-byte stores per lane per iteration (1, 2 or 4); a lane then
+ *         owns 2*chunks (u64) or 4*chunks (u32) work-items, and every store
+ *         instruction of a wavefront covers 1 KiB of contiguous output.
+ * nontemporal: 1 to use non-temporal (streaming) stores.
+ * The output never depends on the configuration. */
+typedef struct rngx_launch {
+    uint32_t block;
+    uint32_t chunks;
+    uint32_t nontemporal;
+} rngx_launch;
+
+/* Set the configuration used by rngx_generate (u32 != 0: rngx_generate_u32).
+ * Errors: RNGX_E_INVAL for values outside the ranges above. */
+int rngx_set_launch(int u32, const rngx_launch *cfg);
+int rngx_get_launch(int u32, rngx_launch *cfg);
+
+/* ------------------------------------------------------------------------ */
+/* Event profiling (the profiler module, Section 4.3; summary of Fig. 3)     */
+/* ------------------------------------------------------------------------ */
+
+#define RNGX_PROF_NAME 32
+#define RNGX_PROF_MAX_AGG 16
+#define RNGX_PROF_MAX_OVERLAP 32
+
+/* One timed operation: its name (INIT_KERNEL, RNG_KERNEL, READ_BUFFER, ...),
+ * an id of the stream (queue) it ran on, and its start and end instants in
+ * nanoseconds from the start of the profiling window. */
+typedef struct rngx_prof_event {
+    char name[RNGX_PROF_NAME];
+    uint64_t queue;
+    uint64_t start_ns;
+    uint64_t end_ns;
+} rngx_prof_event;
+
+typedef struct rngx_prof_agg {
+    char name[RNGX_PROF_NAME];
+    uint64_t count;
+    double abs_s;   /* sum of durations of the events of this name */
+    double rel_pct; /* abs_s as a share of the sum over all events */
+} rngx_prof_agg;
+
+typedef struct rngx_prof_overlap {
+    char name1[RNGX_PROF_NAME];
+    char name2[RNGX_PROF_NAME];
+    double overlap_s; /* summed intersection of events of the two names */
+} rngx_prof_overlap;
+
+/* Profile analysis. Aggregates are sorted by time, descending; overlap rows
+ * by duration, descending. Two events overlap only if they ran on different
+ * queues; an overlap row is an unordered pair of names, printed with the
+ * name of smaller aggregate time first. eff_s = total_s - overlap_s
+ * ("Tot. of all events (eff.)"), device_pct = 100 * eff_s / elapsed_s. */
+typedef struct rngx_prof_stats {
+    uint64_t n_events;
+    uint64_t n_dropped; /* events not logged because the log was full */
+    uint32_t n_agg;
+    uint32_t n_overlap;
+    double total_s;
+    double overlap_s;
+    double eff_s;
+    double elapsed_s; /* host wall clock of the profiling window */
+    double device_pct;
+    double host_pct;
+    rngx_prof_agg agg[RNGX_PROF_MAX_AGG];
+    rngx_prof_overlap overlap[RNGX_PROF_MAX_OVERLAP];
+} rngx_prof_stats;
+
+/* Clear the event log and open a new profiling window (host clock starts). */
+int rngx_profile_start(void);
+
+/* Wait for every logged operation to finish and close the window. */
+int rngx_profile_stop(void);
+
+/* Turn event logging on (default) or off. */
+int rngx_profile_enable(int on);
+
+/* Summary text in the layout of Fig. 3 for the current window (closing it
+ * first if it is open). The text is owned by the library and stays valid
+ * until the next call of rngx_profile. Returns NULL on error. */
+const char *rngx_profile(void);
+
+/* The same analysis as structured data. */
+int rngx_profile_stats(rngx_prof_stats *out);
+
+/* Copy up to cap logged events (closing the window first if it is open);
+ * *n_out receives the number of logged events. */
+int rngx_profile_events(rngx_prof_event *out, uint32_t cap, uint32_t *n_out);
+
+/* Analyse a caller-supplied event table (host memory) with the same code.
+ * Errors: RNGX_E_INVAL if any event ends before it starts, or events is
+ * NULL with n > 0. */
+int rngx_profile_analyze(const rngx_prof_event *events, uint32_t n,
+                         double elapsed_s, rngx_prof_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RNGX_H */

@@ -34,8 +34,9 @@
  * definition and those invariants (parity against the paper unpinned by
  * construction for s != 0).
  */
-#include <stdint.h>
 #include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
 
 /* ------------------------------------------------------------------------- */
 /* Listing S4, "low bits": the six-round 32-bit integer hash (Bob Jenkins'     */
@@ -121,22 +122,38 @@ uint64_t oracle_value(uint64_t seed, uint32_t gid, uint64_t k)
 /* produced `cursor` iterations, the next n_iters iterations are              */
 /*     out[k*n + g] = value(seed, g, cursor + k),  k < n_iters, g < n,        */
 /* iteration-major, which is the byte order the paper's program writes to     */
-/* its standard output. Returns the number of zero values produced (the       */
-/* never-zero invariant says it is always 0).                                 */
+/* its standard output. The loops follow the paper's program: one array of   */
+/* n states; each iteration emits every state, then advances every state one  */
+/* step (Section 5). Returns the number of zero values produced (the          */
+/* never-zero invariant says it is always 0), or UINT64_MAX if the state      */
+/* array cannot be allocated.                                                 */
 /* ------------------------------------------------------------------------- */
+static uint64_t *seeded_states(uint64_t seed, uint32_t n, uint64_t cursor)
+{
+    uint64_t *st = (uint64_t *)malloc((size_t)n * sizeof(uint64_t) + 1);
+    if (!st)
+        return NULL;
+    for (uint32_t g = 0; g < n; ++g)
+        st[g] = oracle_value(seed, g, cursor);
+    return st;
+}
+
 uint64_t oracle_generate(uint64_t seed, uint32_t n, uint64_t cursor,
                          uint32_t n_iters, uint64_t *out)
 {
     uint64_t zeros = 0;
-    for (uint32_t g = 0; g < n; ++g) {
-        uint64_t x = oracle_value(seed, g, cursor);
-        for (uint32_t k = 0; k < n_iters; ++k) {
-            if (x == 0u)
+    uint64_t *st = seeded_states(seed, n, cursor);
+    if (!st)
+        return UINT64_MAX;
+    for (uint32_t k = 0; k < n_iters; ++k) {
+        for (uint32_t g = 0; g < n; ++g) {
+            if (st[g] == 0u)
                 ++zeros;
-            out[(size_t)k * n + g] = x;
-            x = oracle_rng_step(x);
+            out[(size_t)k * n + g] = st[g];
+            st[g] = oracle_rng_step(st[g]);
         }
     }
+    free(st);
     return zeros;
 }
 
@@ -145,15 +162,18 @@ uint64_t oracle_generate_u32(uint64_t seed, uint32_t n, uint64_t cursor,
                              uint32_t n_iters, uint32_t *out)
 {
     uint64_t zeros = 0;
-    for (uint32_t g = 0; g < n; ++g) {
-        uint64_t x = oracle_value(seed, g, cursor);
-        for (uint32_t k = 0; k < n_iters; ++k) {
-            if (x == 0u)
+    uint64_t *st = seeded_states(seed, n, cursor);
+    if (!st)
+        return UINT64_MAX;
+    for (uint32_t k = 0; k < n_iters; ++k) {
+        for (uint32_t g = 0; g < n; ++g) {
+            if (st[g] == 0u)
                 ++zeros;
-            out[(size_t)k * n + g] = (uint32_t)(x & 0xffffffffu);
-            x = oracle_rng_step(x);
+            out[(size_t)k * n + g] = (uint32_t)(st[g] & 0xffffffffu);
+            st[g] = oracle_rng_step(st[g]);
         }
     }
+    free(st);
     return zeros;
 }
 

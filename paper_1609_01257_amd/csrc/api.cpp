@@ -1,0 +1,304 @@
+// C ABI of the generator: context, lifecycle, plain generation, errors.
+//
+// One process-wide context holds the library-owned state buffer, the
+// library's own stream (for the init kernel) and the `state_ready` event
+// that orders every use of the state across caller streams: a generate call
+// makes its stream wait for `state_ready`, launches, and re-records it.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "internal.h"
+
+namespace rngx {
+
+static thread_local std::string t_last_error;
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    const int code = (e == hipErrorOutOfMemory) ? RNGX_E_NOMEM : RNGX_E_HIP;
+    return set_error(code, "%s failed: %s (%s)", what, hipGetErrorName(e), hipGetErrorString(e));
+}
+
+void clear_error() { t_last_error.clear(); }
+
+namespace {
+
+struct Ctx {
+    std::mutex mu;
+    bool inited = false;
+    int device = -1;
+    uint64_t seed = 0;
+    uint32_t n = 0;
+    uint64_t cursor = 0;
+    uint64_t *state = nullptr;
+    hipStream_t lib_stream = nullptr;
+    hipEvent_t state_ready = nullptr;
+    rngx_launch cfg64{256, 2, 0};
+    rngx_launch cfg32{256, 1, 0};
+};
+
+Ctx &ctx()
+{
+    static Ctx *c = new Ctx; // never destroyed: HIP may be torn down at exit
+    return *c;
+}
+
+// Free the state of a previous init (waits for its last use first).
+int release_state_locked(Ctx &c)
+{
+    if (c.state_ready)
+        RNGX_HIP(hipEventSynchronize(c.state_ready));
+    if (c.state) {
+        RNGX_HIP(hipFree(c.state));
+        c.state = nullptr;
+    }
+    c.inited = false;
+    c.n = 0;
+    c.cursor = 0;
+    return RNGX_OK;
+}
+
+int check_device_locked(const Ctx &c)
+{
+    int dev = -1;
+    RNGX_HIP(hipGetDevice(&dev));
+    if (dev != c.device)
+        return set_error(RNGX_E_INVAL,
+                         "the generator lives on device %d but device %d is current", c.device,
+                         dev);
+    return RNGX_OK;
+}
+
+int generate_impl(uint32_t n_iters, void *out, void *stream, bool u32)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    clear_error();
+    if (!c.inited)
+        return set_error(RNGX_E_NOINIT, "generate called before rngx_init");
+    if (n_iters == 0)
+        return RNGX_OK;
+    const size_t esize = u32 ? 4 : 8;
+    if (!out)
+        return set_error(RNGX_E_INVAL, "generate: out is NULL");
+    if (reinterpret_cast<uintptr_t>(out) % esize)
+        return set_error(RNGX_E_INVAL, "generate: out is not %zu-byte aligned", esize);
+    const unsigned __int128 bytes = (unsigned __int128)n_iters * c.n * esize;
+    if (bytes > (unsigned __int128)SIZE_MAX)
+        return set_error(RNGX_E_INVAL, "generate: output size overflows size_t");
+    int rc = check_device_locked(c);
+    if (rc)
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RNGX_HIP(hipStreamWaitEvent(s, c.state_ready, 0));
+    const int tok = prof::begin("RNG_KERNEL", s);
+    hipError_t e = launch_gen(u32 ? c.cfg32 : c.cfg64, u32, c.state, c.n, n_iters, out, s);
+    prof::end(tok, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "rng kernel launch");
+    RNGX_HIP(hipEventRecord(c.state_ready, s));
+    c.cursor += n_iters;
+    return RNGX_OK;
+}
+
+} // namespace
+} // namespace rngx
+
+using namespace rngx;
+
+extern "C" {
+
+int rngx_init(uint64_t seed, uint32_t n_states)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    clear_error();
+    if (n_states == 0)
+        return set_error(RNGX_E_INVAL, "rngx_init: n_states must be at least 1");
+    int rc = release_state_locked(c);
+    if (rc)
+        return rc;
+    int dev = -1;
+    RNGX_HIP(hipGetDevice(&dev));
+    if (c.lib_stream && dev != c.device) {
+        // Resources belong to another device: recreate them here.
+        (void)hipStreamDestroy(c.lib_stream);
+        (void)hipEventDestroy(c.state_ready);
+        c.lib_stream = nullptr;
+        c.state_ready = nullptr;
+    }
+    c.device = dev;
+    if (!c.lib_stream)
+        RNGX_HIP(hipStreamCreateWithFlags(&c.lib_stream, hipStreamNonBlocking));
+    if (!c.state_ready)
+        RNGX_HIP(hipEventCreateWithFlags(&c.state_ready, hipEventDisableTiming));
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, (size_t)n_states * sizeof(uint64_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(RNGX_E_NOMEM, "rngx_init: cannot allocate %zu bytes of state: %s",
+                         (size_t)n_states * sizeof(uint64_t), hipGetErrorString(e));
+    }
+    c.state = static_cast<uint64_t *>(p);
+    rc = prof::start(c.lib_stream);
+    if (rc)
+        return rc;
+    const int tok = prof::begin("INIT_KERNEL", c.lib_stream);
+    e = launch_init(c.state, n_states, seed_mix(seed), c.lib_stream);
+    prof::end(tok, c.lib_stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "init kernel launch");
+    RNGX_HIP(hipEventRecord(c.state_ready, c.lib_stream));
+    c.seed = seed;
+    c.n = n_states;
+    c.cursor = 0;
+    c.inited = true;
+    return RNGX_OK;
+}
+
+int rngx_generate(uint32_t n_iters, uint64_t *out, void *stream)
+{
+    return generate_impl(n_iters, out, stream, false);
+}
+
+int rngx_generate_u32(uint32_t n_iters, uint32_t *out, void *stream)
+{
+    return generate_impl(n_iters, out, stream, true);
+}
+
+int rngx_info(uint64_t *seed, uint32_t *n_states, uint64_t *cursor)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    clear_error();
+    if (!c.inited)
+        return set_error(RNGX_E_NOINIT, "rngx_info called before rngx_init");
+    if (seed)
+        *seed = c.seed;
+    if (n_states)
+        *n_states = c.n;
+    if (cursor)
+        *cursor = c.cursor;
+    return RNGX_OK;
+}
+
+int rngx_shutdown(void)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    clear_error();
+    int rc = release_state_locked(c);
+    prof::release_all();
+    if (c.state_ready)
+        (void)hipEventDestroy(c.state_ready);
+    if (c.lib_stream)
+        (void)hipStreamDestroy(c.lib_stream);
+    c.state_ready = nullptr;
+    c.lib_stream = nullptr;
+    c.device = -1;
+    return rc;
+}
+
+const char *rngx_last_error(void) { return t_last_error.c_str(); }
+
+const char *rngx_strerror(int code)
+{
+    switch (code) {
+    case RNGX_OK: return "RNGX_OK: success";
+    case RNGX_E_INVAL: return "RNGX_E_INVAL: invalid argument";
+    case RNGX_E_NOINIT: return "RNGX_E_NOINIT: generator not initialised";
+    case RNGX_E_HIP: return "RNGX_E_HIP: HIP runtime error";
+    case RNGX_E_NOMEM: return "RNGX_E_NOMEM: out of device memory";
+    case RNGX_E_BUSY: return "RNGX_E_BUSY: resource full, retry later";
+    default: return "unknown rngx status code";
+    }
+}
+
+int rngx_set_launch(int u32, const rngx_launch *cfg)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    clear_error();
+    if (!cfg || !launch_cfg_valid(*cfg))
+        return set_error(RNGX_E_INVAL,
+                         "rngx_set_launch: block must be 64..1024 in steps of 64, chunks 1, 2 "
+                         "or 4, nontemporal 0 or 1");
+    (u32 ? c.cfg32 : c.cfg64) = *cfg;
+    return RNGX_OK;
+}
+
+int rngx_get_launch(int u32, rngx_launch *cfg)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    clear_error();
+    if (!cfg)
+        return set_error(RNGX_E_INVAL, "rngx_get_launch: NULL");
+    *cfg = u32 ? c.cfg32 : c.cfg64;
+    return RNGX_OK;
+}
+
+int rngx_profile_start(void)
+{
+    Ctx &c = ctx();
+    std::lock_guard<std::mutex> lk(c.mu);
+    clear_error();
+    if (!c.lib_stream)
+        return set_error(RNGX_E_NOINIT, "rngx_profile_start called before rngx_init");
+    return prof::start(c.lib_stream);
+}
+
+int rngx_profile_stop(void)
+{
+    clear_error();
+    return prof::stop();
+}
+
+int rngx_profile_enable(int on)
+{
+    clear_error();
+    return prof::enable(on);
+}
+
+const char *rngx_profile(void)
+{
+    clear_error();
+    return prof::summary();
+}
+
+int rngx_profile_stats(rngx_prof_stats *out)
+{
+    clear_error();
+    if (!out)
+        return set_error(RNGX_E_INVAL, "rngx_profile_stats: NULL");
+    return prof::stats(out);
+}
+
+int rngx_profile_events(rngx_prof_event *out, uint32_t cap, uint32_t *n_out)
+{
+    clear_error();
+    return prof::events(out, cap, n_out);
+}
+
+int rngx_profile_analyze(const rngx_prof_event *events, uint32_t n, double elapsed_s,
+                         rngx_prof_stats *out)
+{
+    clear_error();
+    return analyze_table(events, n, elapsed_s, out);
+}
+
+} // extern "C"

@@ -1,0 +1,244 @@
+"""ctypes binding of librngx.so (the C ABI declared in include/rngx.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels and host code. Functions take torch tensors for device buffers and
+torch streams (or raw handles) for streams, and raise :class:`RngxError` on a
+non-zero status. The binding refuses to run without the built library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librngx.so")
+
+RNGX_OK = 0
+RNGX_E_INVAL = -1
+RNGX_E_NOINIT = -2
+RNGX_E_HIP = -3
+RNGX_E_NOMEM = -4
+RNGX_E_BUSY = -5
+
+PROF_NAME = 32
+PROF_MAX_AGG = 16
+PROF_MAX_OVERLAP = 32
+
+
+class RngxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (strerror(code), msg))
+        self.code = code
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
+                ("nontemporal", ctypes.c_uint32)]
+
+
+class ProfEvent(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * PROF_NAME), ("queue", ctypes.c_uint64),
+                ("start_ns", ctypes.c_uint64), ("end_ns", ctypes.c_uint64)]
+
+
+class ProfAgg(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * PROF_NAME), ("count", ctypes.c_uint64),
+                ("abs_s", ctypes.c_double), ("rel_pct", ctypes.c_double)]
+
+
+class ProfOverlap(ctypes.Structure):
+    _fields_ = [("name1", ctypes.c_char * PROF_NAME), ("name2", ctypes.c_char * PROF_NAME),
+                ("overlap_s", ctypes.c_double)]
+
+
+class ProfStats(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_uint64), ("n_dropped", ctypes.c_uint64),
+                ("n_agg", ctypes.c_uint32), ("n_overlap", ctypes.c_uint32),
+                ("total_s", ctypes.c_double), ("overlap_s", ctypes.c_double),
+                ("eff_s", ctypes.c_double), ("elapsed_s", ctypes.c_double),
+                ("device_pct", ctypes.c_double), ("host_pct", ctypes.c_double),
+                ("agg", ProfAgg * PROF_MAX_AGG), ("overlap", ProfOverlap * PROF_MAX_OVERLAP)]
+
+
+_lib = None
+
+_u32, _u64, _int, _p = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p
+_SIGS = {
+    "rngx_init": ([_u64, _u32], _int),
+    "rngx_generate": ([_u32, _p, _p], _int),
+    "rngx_generate_u32": ([_u32, _p, _p], _int),
+    "rngx_info": ([_p, _p, _p], _int),
+    "rngx_shutdown": ([], _int),
+    "rngx_last_error": ([], ctypes.c_char_p),
+    "rngx_strerror": ([_int], ctypes.c_char_p),
+    "rngx_set_launch": ([_int, ctypes.POINTER(Launch)], _int),
+    "rngx_get_launch": ([_int, ctypes.POINTER(Launch)], _int),
+    "rngx_profile_start": ([], _int),
+    "rngx_profile_stop": ([], _int),
+    "rngx_profile_enable": ([_int], _int),
+    "rngx_profile": ([], ctypes.c_char_p),
+    "rngx_profile_stats": ([ctypes.POINTER(ProfStats)], _int),
+    "rngx_profile_events": ([_p, _u32, ctypes.POINTER(_u32)], _int),
+    "rngx_profile_analyze": ([_p, _u32, ctypes.c_double, ctypes.POINTER(ProfStats)], _int),
+}
+
+
+def lib():
+    """Load librngx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librngx.so is not built (expected at %s); run "
+                               "`python -m paper_1609_01257_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().rngx_strerror(code).decode()
+
+
+def last_error() -> str:
+    return lib().rngx_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != RNGX_OK:
+        raise RngxError(rc, last_error())
+
+
+def stream_handle(stream) -> int:
+    """hipStream_t of a torch stream, a raw integer handle, or the current stream."""
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _device_buffer(t, esize: int, need: int) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("output must be a CUDA (HIP) torch tensor")
+    if t.element_size() != esize or t.dtype.is_floating_point:
+        raise TypeError("output must be a %d-byte integer tensor" % esize)
+    if not t.is_contiguous():
+        raise ValueError("output must be contiguous")
+    if t.numel() < need:
+        raise ValueError("output holds %d elements, %d needed" % (t.numel(), need))
+    return t.data_ptr()
+
+
+# --- generator --------------------------------------------------------------
+
+def init(seed: int, n_states: int):
+    _check(lib().rngx_init(seed & (2**64 - 1), n_states))
+
+
+def info():
+    s, n, c = _u64(), _u32(), _u64()
+    _check(lib().rngx_info(ctypes.byref(s), ctypes.byref(n), ctypes.byref(c)))
+    return s.value, n.value, c.value
+
+
+def generate(n_iters: int, out, stream=None):
+    """out[k * n + g] = V(seed, g, cursor + k) for k < n_iters (uint64/int64 tensor)."""
+    n = info()[1]
+    ptr = _device_buffer(out, 8, n_iters * n) if n_iters else (out.data_ptr() if out is not None else 0)
+    _check(lib().rngx_generate(n_iters, ptr, stream_handle(stream)))
+
+
+def generate_u32(n_iters: int, out, stream=None):
+    """Low 32-bit halves of :func:`generate` (uint32/int32 tensor)."""
+    n = info()[1]
+    ptr = _device_buffer(out, 4, n_iters * n) if n_iters else (out.data_ptr() if out is not None else 0)
+    _check(lib().rngx_generate_u32(n_iters, ptr, stream_handle(stream)))
+
+
+def generate_ptr(n_iters: int, ptr: int, stream: int = 0, u32: bool = False) -> int:
+    """Raw call (returns the status instead of raising); for ABI tests."""
+    f = lib().rngx_generate_u32 if u32 else lib().rngx_generate
+    return f(n_iters, ptr, stream)
+
+
+def shutdown():
+    _check(lib().rngx_shutdown())
+
+
+def set_launch(u32: bool, block: int, chunks: int, nontemporal: bool = False):
+    cfg = Launch(block, chunks, int(bool(nontemporal)))
+    _check(lib().rngx_set_launch(int(u32), ctypes.byref(cfg)))
+
+
+def get_launch(u32: bool):
+    cfg = Launch()
+    _check(lib().rngx_get_launch(int(u32), ctypes.byref(cfg)))
+    return {"block": cfg.block, "chunks": cfg.chunks, "nontemporal": bool(cfg.nontemporal)}
+
+
+# --- profiling ----------------------------------------------------------------
+
+def profile_start():
+    _check(lib().rngx_profile_start())
+
+
+def profile_stop():
+    _check(lib().rngx_profile_stop())
+
+
+def profile_enable(on: bool):
+    _check(lib().rngx_profile_enable(int(bool(on))))
+
+
+def profile() -> str:
+    s = lib().rngx_profile()
+    if s is None:
+        raise RngxError(RNGX_E_INVAL, last_error())
+    return s.decode()
+
+
+def _stats_dict(st: ProfStats) -> dict:
+    return {
+        "n_events": st.n_events, "n_dropped": st.n_dropped,
+        "total_s": st.total_s, "overlap_s": st.overlap_s, "eff_s": st.eff_s,
+        "elapsed_s": st.elapsed_s, "device_pct": st.device_pct, "host_pct": st.host_pct,
+        "agg": [(st.agg[i].name.decode(), st.agg[i].count, st.agg[i].abs_s, st.agg[i].rel_pct)
+                for i in range(st.n_agg)],
+        "overlaps": [(st.overlap[i].name1.decode(), st.overlap[i].name2.decode(),
+                      st.overlap[i].overlap_s) for i in range(st.n_overlap)],
+    }
+
+
+def profile_stats() -> dict:
+    st = ProfStats()
+    _check(lib().rngx_profile_stats(ctypes.byref(st)))
+    return _stats_dict(st)
+
+
+def profile_events() -> list:
+    n = _u32()
+    _check(lib().rngx_profile_events(None, 0, ctypes.byref(n)))
+    arr = (ProfEvent * max(1, n.value))()
+    _check(lib().rngx_profile_events(arr, n.value, ctypes.byref(n)))
+    return [(arr[i].name.decode(), arr[i].queue, arr[i].start_ns, arr[i].end_ns)
+            for i in range(n.value)]
+
+
+def profile_analyze(events, elapsed_s: float) -> dict:
+    """Analyse (name, queue, start_ns, end_ns) rows with the library's code."""
+    arr = (ProfEvent * max(1, len(events)))()
+    qid = {}
+    for i, (name, q, s, e) in enumerate(events):
+        arr[i].name = name.encode()[:PROF_NAME - 1]
+        arr[i].queue = q if isinstance(q, int) else qid.setdefault(q, len(qid))
+        arr[i].start_ns = s
+        arr[i].end_ns = e
+    st = ProfStats()
+    _check(lib().rngx_profile_analyze(arr, len(events), elapsed_s, ctypes.byref(st)))
+    return _stats_dict(st)

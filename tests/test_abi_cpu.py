@@ -1,0 +1,104 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/rngx.h declares, reports errors without a GPU, and its host-side
+profile analysis matches the oracle's (oracle/profile.py)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1609_01257_amd import rngx
+from oracle import profile as oprof
+from tests.test_profile_oracle import fig3_events
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rngx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rngx_\w+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    L = ctypes.CDLL(rngx.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    assert set(declared_functions()) <= set(rngx._SIGS)
+
+
+def test_strerror_and_codes():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert rngx.strerror(code).startswith("RNGX_")
+    assert "unknown" in rngx.strerror(-99)
+
+
+def test_generate_before_init_is_noinit():
+    rngx.shutdown()
+    assert rngx.generate_ptr(4, 0) == rngx.RNGX_E_NOINIT
+    assert "before rngx_init" in rngx.last_error()
+    with pytest.raises(rngx.RngxError):
+        rngx.info()
+
+
+def test_init_zero_states_is_inval():
+    assert rngx.lib().rngx_init(0, 0) == rngx.RNGX_E_INVAL
+
+
+def test_set_launch_validation():
+    for bad in [(32, 1, 0), (1088, 1, 0), (100, 1, 0), (256, 3, 0), (256, 0, 0), (256, 1, 2)]:
+        cfg = rngx.Launch(*bad)
+        assert rngx.lib().rngx_set_launch(0, ctypes.byref(cfg)) == rngx.RNGX_E_INVAL
+    rngx.set_launch(False, 512, 4, True)
+    assert rngx.get_launch(False) == {"block": 512, "chunks": 4, "nontemporal": True}
+    rngx.set_launch(False, 256, 2, False)
+
+
+def _cmp(lib_stats, orc):
+    assert lib_stats["n_events"] >= 0
+    assert [(a, c) for a, c, _, _ in lib_stats["agg"]] == [(a, c) for a, c, _, _ in orc.agg]
+    for (_, _, s1, r1), (_, _, s2, r2) in zip(lib_stats["agg"], orc.agg):
+        assert s1 == pytest.approx(s2, rel=1e-12, abs=1e-18)
+        assert r1 == pytest.approx(r2, rel=1e-12, abs=1e-12)
+    assert [(a, b) for a, b, _ in lib_stats["overlaps"]] == [(a, b) for a, b, _ in orc.overlaps]
+    for (_, _, o1), (_, _, o2) in zip(lib_stats["overlaps"], orc.overlaps):
+        assert o1 == pytest.approx(o2, rel=1e-12, abs=1e-18)
+    for k in ("total_s", "overlap_s", "eff_s", "elapsed_s", "device_pct", "host_pct"):
+        assert lib_stats[k] == pytest.approx(getattr(orc, k), rel=1e-12, abs=1e-15), k
+
+
+def test_profile_analyze_fig3_matches_oracle():
+    ev = fig3_events()
+    rows = [(e.name, e.queue, e.start_ns, e.end_ns) for e in ev]
+    _cmp(rngx.profile_analyze(rows, 9.054619), oprof.analyze(ev, 9.054619))
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_profile_analyze_random_matches_oracle(seed):
+    rng = np.random.default_rng(100 + seed)
+    nq = int(rng.integers(1, 5))
+    rows = []
+    for q in range(nq):
+        t = int(rng.integers(0, 50))
+        for _ in range(int(rng.integers(0, 40))):
+            d = int(rng.integers(0, 30))
+            rows.append((str(rng.choice(["INIT_KERNEL", "RNG_KERNEL", "READ_BUFFER", "X"])),
+                         q, t, t + d))
+            t += d + int(rng.integers(0, 10))
+    # Sprinkle some events that overlap within one queue as well.
+    if rows and seed % 3 == 0:
+        n0, q0, s0, e0 = rows[0]
+        rows.append((n0, q0, s0 + 1, e0 + 5))
+    ev = [oprof.Event(n, str(q), s, e) for n, q, s, e in rows]
+    _cmp(rngx.profile_analyze(rows, 1e-6 * (1 + seed)), oprof.analyze(ev, 1e-6 * (1 + seed)))
+
+
+def test_profile_analyze_rejects_backwards_event():
+    with pytest.raises(rngx.RngxError):
+        rngx.profile_analyze([("K", 0, 10, 5)], 1.0)
