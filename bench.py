@@ -29,6 +29,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def counter_traffic(launch):
+    """HBM bytes per launch of the headline kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source
+    or its launch configuration changed since those counters were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1609_01257_amd", "csrc", "kernels.hip")
+    summary = os.path.join(ROOT, "profiles", "gen_kernel_u64_2p26x256.md")
+    try:
+        line = [l for l in open(summary) if l.startswith("machine:")][0]
+    except (OSError, IndexError):
+        return None
+    kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    cfg = "%d,%d,%d" % (launch["block"], launch["chunks"], int(launch["nontemporal"]))
+    if kv.get("kernels_hip_sha256_16") != digest or kv.get("launch") != cfg:
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def kernel_avg_s(stats, name):
     for agg_name, count, abs_s, _ in stats["agg"]:
         if agg_name == name:
@@ -82,6 +101,58 @@ def sweep(torch, rngx, reps):
     return rows
 
 
+def streaming(torch, rngx):
+    """Paper-shaped streaming: 4,194,304 streams, seed 42, 2,000 iterations of
+    32 MiB, generation and device-to-host copies overlapped on two streams
+    through two device buffers and two pinned host slots (no host consumer,
+    as in the paper's runs with output sent to the null device)."""
+    from paper_1609_01257_amd import inputs
+    cfg = inputs.STREAMING
+    n, steps = cfg["n"], cfg["iters"]
+    dev0 = torch.empty(n, dtype=torch.int64, device="cuda")
+    dev1 = torch.empty(n, dtype=torch.int64, device="cuda")
+    host = torch.empty(2 * n, dtype=torch.int64, pin_memory=True)
+    rngx.init(cfg["seed"], n)
+    rngx.stream_to_host(16, 1, dev0, dev1, host, 2)          # warm-up
+    rngx.init(cfg["seed"], n)                                # restarts the profile window
+    t0 = time.perf_counter()
+    rngx.stream_to_host(steps, 1, dev0, dev1, host, 2)
+    t1 = time.perf_counter()
+    st = rngx.profile_stats()
+    log(rngx.profile())
+    agg = {name: (c, a) for name, c, a, _ in st["agg"]}
+    step_bytes = 8 * n
+    # Practical host-link ceiling: back-to-back pinned copies of one step.
+    s = torch.cuda.Stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s):
+        for _ in range(5):
+            host[:n].copy_(dev0, non_blocking=True)
+        e0.record(s)
+        reps = 100
+        for _ in range(reps):
+            host[:n].copy_(dev0, non_blocking=True)
+        e1.record(s)
+    s.synchronize()
+    peak = step_bytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del dev0, dev1, host
+    torch.cuda.empty_cache()
+    reads = agg.get("READ_BUFFER", (0, 0.0))
+    kern = agg.get("RNG_KERNEL", (0, 0.0))
+    return {
+        "workload": "4,194,304 streams, seed 42, 2,000 iterations x 32 MiB to pinned host",
+        "wall_s": round(t1 - t0, 4),
+        "host_link_gbs": round(step_bytes * steps / (t1 - t0) / 1e9, 2),
+        "read_gbs": round(step_bytes * reads[0] / reads[1] / 1e9, 2) if reads[1] else None,
+        "pinned_copy_peak_gbs": round(peak, 2),
+        "pcie5_x16_theoretical_gbs": 63.0,
+        "rng_kernel_s": round(kern[1], 6), "rng_kernel_count": kern[0],
+        "read_buffer_s": round(reads[1], 6), "read_buffer_count": reads[0],
+        "overlap_s": round(st["overlap_s"], 6), "eff_s": round(st["eff_s"], 6),
+        "elapsed_s": round(st["elapsed_s"], 6), "device_pct": round(st["device_pct"], 2),
+    }
+
+
 def cpu_baseline(n_total, iters):
     """The CPU oracle, single-threaded, on the first 2^20 work-items of the
     workload (all iterations)."""
@@ -106,6 +177,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline kernel (for profiling)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 16 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -117,6 +190,16 @@ def main():
     from paper_1609_01257_amd import rngx
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        # A plain copy of known size: reads and writes exactly 16 GiB each, so
+        # HBM byte counters read on it give their scale factor.
+        src = torch.ones(2 << 30, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
+        return
     n, iters, seed = 1 << 26, 256, 1
     log("headline: plain u64, n=2^26, iters=256, warmup=%d steps=%d" % (args.warmup, args.steps))
     head = plain_run(torch, rngx, seed, n, iters, False, args.warmup, args.steps)
@@ -142,7 +225,7 @@ def main():
                      "achieved": round(head["kernel_gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(head["kernel_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": counter_traffic(rngx.get_launch(False)),
                      "kernel": "gen_kernel<u64>",
                      "kernel_avg_ms": round(head["kernel_avg_s"] * 1e3, 4),
                      "alg_bytes_per_launch": head["alg_bytes_per_launch"]},
@@ -155,6 +238,9 @@ def main():
                          "frac_hbm": round(h32["kernel_gbs"] / HBM_PEAK_GBS, 4)}
         if not args.no_sweep:
             result["sweep"] = sweep(torch, rngx, 3)
+        log("streaming (two-stream device-to-host pipeline)")
+        result["streaming"] = streaming(torch, rngx)
+        log("streaming:", result["streaming"])
     rngx.shutdown()
     if not args.no_cpu_baseline and not args.headline_only:
         log("cpu baseline (oracle) ...")

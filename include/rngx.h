@@ -51,6 +51,7 @@ extern "C" {
 #define RNGX_E_HIP (-3)    /* HIP runtime error; rngx_last_error() holds its text */
 #define RNGX_E_NOMEM (-4)  /* device allocation failed */
 #define RNGX_E_BUSY (-5)   /* resource temporarily full; retry later */
+#define RNGX_E_ABORTED (-6) /* a caller-supplied consumer asked to stop */
 
 /* ------------------------------------------------------------------------ */
 /* Generator lifecycle                                                       */
@@ -118,6 +119,44 @@ typedef struct rngx_launch {
  * Errors: RNGX_E_INVAL for values outside the ranges above. */
 int rngx_set_launch(int u32, const rngx_launch *cfg);
 int rngx_get_launch(int u32, rngx_launch *cfg);
+
+/* ------------------------------------------------------------------------ */
+/* Streaming to host memory (Section 5, Fig. 2)                              */
+/* ------------------------------------------------------------------------ */
+
+/* Host-side consumer of one streamed step: `values` points at the step's
+ * host slot (bytes = iters_per_step * n_states * element size), `step` is
+ * its index from 0. It runs on the thread that called rngx_stream_to_host,
+ * in step order. Return 0 to continue, non-zero to stop the stream. It may
+ * call rngx functions; generate calls made from it advance the same cursor. */
+typedef int (*rngx_consume_fn)(void *user, uint64_t step, const void *values, size_t bytes);
+
+/* Stream n_steps * iters_per_step iterations to host memory with generation
+ * and device-to-host copies overlapped on two streams (Section 5: the init
+ * and rng kernels run on one command queue, the reads on a second one, with
+ * device-side double buffering).
+ * Step k generates iters_per_step iterations (exactly as rngx_generate /
+ * rngx_generate_u32 would, continuing the cursor) into device buffer k % 2
+ * (dev0 or dev1, each of dev_bytes bytes) on gen_stream, then copies them to
+ * host slot k % host_slots of `host` on copy_stream. Step k's generation
+ * waits only for the copy of step k - 2; step k's copy waits for its
+ * generation. Kernels are profiled as RNG_KERNEL and copies as READ_BUFFER.
+ * host: host_slots consecutive slots of one step each; page-locked memory
+ *       (hipHostMalloc, or torch pin_memory) makes the copies asynchronous.
+ * consume: optional (NULL = no host consumer, as when the paper's output is
+ *       sent to the null device); with it, a slot is refilled only after the
+ *       consumer returned for the step it held.
+ * gen_stream, copy_stream: distinct streams, or NULL for the library's own
+ *       pair. The call returns when every copy has completed (and every
+ *       step has been consumed).
+ * Errors: RNGX_E_NOINIT; RNGX_E_INVAL (NULL/equal/misaligned buffers, a
+ * step larger than dev_bytes, host_slots == 0, equal streams);
+ * RNGX_E_ABORTED when the consumer stops the stream (steps generated so far
+ * have advanced the cursor); RNGX_E_HIP. */
+int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, int u32, void *dev0,
+                        void *dev1, size_t dev_bytes, void *host, uint32_t host_slots,
+                        rngx_consume_fn consume, void *user, void *gen_stream,
+                        void *copy_stream);
 
 /* ------------------------------------------------------------------------ */
 /* Event profiling (the profiler module, Section 4.3; summary of Fig. 3)     */

@@ -1,9 +1,10 @@
 // C ABI of the generator: context, lifecycle, plain generation, errors.
 //
-// One process-wide context holds the library-owned state buffer, the
-// library's own stream (for the init kernel) and the `state_ready` event
-// that orders every use of the state across caller streams: a generate call
-// makes its stream wait for `state_ready`, launches, and re-records it.
+// One process-wide context (Generator, internal.h) holds the library-owned
+// state buffer, the library's own stream (for the init kernel) and the
+// `state_ready` event that orders every use of the state across caller
+// streams: a generate call makes its stream wait for `state_ready`,
+// launches, and re-records it.
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -35,30 +36,16 @@ int hip_fail(hipError_t e, const char *what)
 
 void clear_error() { t_last_error.clear(); }
 
-namespace {
-
-struct Ctx {
-    std::mutex mu;
-    bool inited = false;
-    int device = -1;
-    uint64_t seed = 0;
-    uint32_t n = 0;
-    uint64_t cursor = 0;
-    uint64_t *state = nullptr;
-    hipStream_t lib_stream = nullptr;
-    hipEvent_t state_ready = nullptr;
-    rngx_launch cfg64{256, 2, 0};
-    rngx_launch cfg32{256, 1, 0};
-};
-
-Ctx &ctx()
+Generator &generator()
 {
-    static Ctx *c = new Ctx; // never destroyed: HIP may be torn down at exit
-    return *c;
+    static Generator *g = new Generator; // never destroyed: HIP may be gone at exit
+    return *g;
 }
 
+namespace {
+
 // Free the state of a previous init (waits for its last use first).
-int release_state_locked(Ctx &c)
+int release_state_locked(Generator &c)
 {
     if (c.state_ready)
         RNGX_HIP(hipEventSynchronize(c.state_ready));
@@ -72,7 +59,17 @@ int release_state_locked(Ctx &c)
     return RNGX_OK;
 }
 
-int check_device_locked(const Ctx &c)
+int generate_impl(uint32_t n_iters, void *out, void *stream, bool u32)
+{
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    clear_error();
+    return generate_locked(c, n_iters, out, static_cast<hipStream_t>(stream), u32);
+}
+
+} // namespace
+
+int check_device_locked(const Generator &c)
 {
     int dev = -1;
     RNGX_HIP(hipGetDevice(&dev));
@@ -83,11 +80,8 @@ int check_device_locked(const Ctx &c)
     return RNGX_OK;
 }
 
-int generate_impl(uint32_t n_iters, void *out, void *stream, bool u32)
+int generate_locked(Generator &c, uint32_t n_iters, void *out, hipStream_t s, bool u32)
 {
-    Ctx &c = ctx();
-    std::lock_guard<std::mutex> lk(c.mu);
-    clear_error();
     if (!c.inited)
         return set_error(RNGX_E_NOINIT, "generate called before rngx_init");
     if (n_iters == 0)
@@ -103,7 +97,6 @@ int generate_impl(uint32_t n_iters, void *out, void *stream, bool u32)
     int rc = check_device_locked(c);
     if (rc)
         return rc;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     RNGX_HIP(hipStreamWaitEvent(s, c.state_ready, 0));
     const int tok = prof::begin("RNG_KERNEL", s);
     hipError_t e = launch_gen(u32 ? c.cfg32 : c.cfg64, u32, c.state, c.n, n_iters, out, s);
@@ -115,7 +108,6 @@ int generate_impl(uint32_t n_iters, void *out, void *stream, bool u32)
     return RNGX_OK;
 }
 
-} // namespace
 } // namespace rngx
 
 using namespace rngx;
@@ -124,8 +116,8 @@ extern "C" {
 
 int rngx_init(uint64_t seed, uint32_t n_states)
 {
-    Ctx &c = ctx();
-    std::lock_guard<std::mutex> lk(c.mu);
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
     clear_error();
     if (n_states == 0)
         return set_error(RNGX_E_INVAL, "rngx_init: n_states must be at least 1");
@@ -182,8 +174,8 @@ int rngx_generate_u32(uint32_t n_iters, uint32_t *out, void *stream)
 
 int rngx_info(uint64_t *seed, uint32_t *n_states, uint64_t *cursor)
 {
-    Ctx &c = ctx();
-    std::lock_guard<std::mutex> lk(c.mu);
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
     clear_error();
     if (!c.inited)
         return set_error(RNGX_E_NOINIT, "rngx_info called before rngx_init");
@@ -198,10 +190,11 @@ int rngx_info(uint64_t *seed, uint32_t *n_states, uint64_t *cursor)
 
 int rngx_shutdown(void)
 {
-    Ctx &c = ctx();
-    std::lock_guard<std::mutex> lk(c.mu);
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
     clear_error();
     int rc = release_state_locked(c);
+    release_pipeline_locked(c);
     prof::release_all();
     if (c.state_ready)
         (void)hipEventDestroy(c.state_ready);
@@ -224,14 +217,15 @@ const char *rngx_strerror(int code)
     case RNGX_E_HIP: return "RNGX_E_HIP: HIP runtime error";
     case RNGX_E_NOMEM: return "RNGX_E_NOMEM: out of device memory";
     case RNGX_E_BUSY: return "RNGX_E_BUSY: resource full, retry later";
+    case RNGX_E_ABORTED: return "RNGX_E_ABORTED: stopped by the caller's consumer";
     default: return "unknown rngx status code";
     }
 }
 
 int rngx_set_launch(int u32, const rngx_launch *cfg)
 {
-    Ctx &c = ctx();
-    std::lock_guard<std::mutex> lk(c.mu);
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
     clear_error();
     if (!cfg || !launch_cfg_valid(*cfg))
         return set_error(RNGX_E_INVAL,
@@ -243,8 +237,8 @@ int rngx_set_launch(int u32, const rngx_launch *cfg)
 
 int rngx_get_launch(int u32, rngx_launch *cfg)
 {
-    Ctx &c = ctx();
-    std::lock_guard<std::mutex> lk(c.mu);
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
     clear_error();
     if (!cfg)
         return set_error(RNGX_E_INVAL, "rngx_get_launch: NULL");
@@ -254,8 +248,8 @@ int rngx_get_launch(int u32, rngx_launch *cfg)
 
 int rngx_profile_start(void)
 {
-    Ctx &c = ctx();
-    std::lock_guard<std::mutex> lk(c.mu);
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
     clear_error();
     if (!c.lib_stream)
         return set_error(RNGX_E_NOINIT, "rngx_profile_start called before rngx_init");

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "rngx.h"
@@ -86,6 +87,31 @@ hipError_t launch_init(uint64_t *state, uint32_t n, const SeedMix &mix, hipStrea
 hipError_t launch_gen(const rngx_launch &cfg, bool u32, uint64_t *state, uint32_t n,
                       uint32_t iters, void *out, hipStream_t s);
 bool launch_cfg_valid(const rngx_launch &cfg);
+
+// ---- the process-wide generator context (api.cpp) --------------------------
+struct Generator {
+    std::recursive_mutex mu; // re-entrant: a stream consumer may call back in
+    bool inited = false;
+    int device = -1;
+    uint64_t seed = 0;
+    uint32_t n = 0;
+    uint64_t cursor = 0;
+    uint64_t *state = nullptr;       // n states, library-owned device memory
+    hipStream_t lib_stream = nullptr; // the init kernel's stream
+    hipEvent_t state_ready = nullptr; // last use of `state` (any stream)
+    rngx_launch cfg64{512, 4, 0}; // fastest measured at 2^26 x 256 on MI355X
+    rngx_launch cfg32{512, 2, 0};
+    // Streams and events of the device-to-host pipeline (pipeline.cpp).
+    hipStream_t pipe_gen = nullptr, pipe_copy = nullptr;
+    hipEvent_t gen_done[2] = {nullptr, nullptr};
+    hipEvent_t copy_done[2] = {nullptr, nullptr};
+};
+
+Generator &generator();
+// Enqueue n_iters iterations into `out` on stream `s`; caller holds g.mu.
+int generate_locked(Generator &g, uint32_t n_iters, void *out, hipStream_t s, bool u32);
+int check_device_locked(const Generator &g);
+void release_pipeline_locked(Generator &g);
 
 // ---- profiler (profiler.cpp) ----------------------------------------------
 namespace prof {

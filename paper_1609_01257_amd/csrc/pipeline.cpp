@@ -1,0 +1,179 @@
+// Two-stream, double-buffered device-to-host streaming of generator output
+// (Section 5 and Fig. 2: kernels on one queue, device-to-host reads on
+// another, device-side double buffering so that each kernel overlaps the
+// previous read).
+//
+// Step k generates `iters_per_step` iterations into device buffer k % 2 on
+// the generation stream and copies it into host slot k % host_slots on the
+// copy stream. HIP events replace the paper's two semaphores:
+//   - the copy of step k waits for `gen_done[k % 2]` (generation k finished);
+//   - generation k waits for `copy_done[k % 2]` (the copy of step k - 2,
+//     which read the same device buffer, finished).
+// Here the output buffers are double-buffered, not the state (the state
+// stays in a library buffer and, inside one launch, in registers), so
+// generation of step k + 1 may run while step k is still being copied.
+// If a consumer is given, it is called on this thread for every step in
+// order once its copy is complete, and a host slot is reused only after the
+// consumer has returned for the step it held (host-side multi-buffering, the
+// paper's suggested improvement in Section 5).
+#include <vector>
+
+#include "internal.h"
+
+namespace rngx {
+
+void release_pipeline_locked(Generator &g)
+{
+    if (g.pipe_copy)
+        (void)hipStreamSynchronize(g.pipe_copy);
+    if (g.pipe_gen)
+        (void)hipStreamSynchronize(g.pipe_gen);
+    for (int i = 0; i < 2; ++i) {
+        if (g.gen_done[i])
+            (void)hipEventDestroy(g.gen_done[i]);
+        if (g.copy_done[i])
+            (void)hipEventDestroy(g.copy_done[i]);
+        g.gen_done[i] = g.copy_done[i] = nullptr;
+    }
+    if (g.pipe_gen)
+        (void)hipStreamDestroy(g.pipe_gen);
+    if (g.pipe_copy)
+        (void)hipStreamDestroy(g.pipe_copy);
+    g.pipe_gen = g.pipe_copy = nullptr;
+}
+
+namespace {
+
+int ensure_pipeline_locked(Generator &g)
+{
+    if (!g.pipe_gen)
+        RNGX_HIP(hipStreamCreateWithFlags(&g.pipe_gen, hipStreamNonBlocking));
+    if (!g.pipe_copy)
+        RNGX_HIP(hipStreamCreateWithFlags(&g.pipe_copy, hipStreamNonBlocking));
+    for (int i = 0; i < 2; ++i) {
+        if (!g.gen_done[i])
+            RNGX_HIP(hipEventCreateWithFlags(&g.gen_done[i], hipEventDisableTiming));
+        if (!g.copy_done[i])
+            RNGX_HIP(hipEventCreateWithFlags(&g.copy_done[i], hipEventDisableTiming));
+    }
+    return RNGX_OK;
+}
+
+struct SlotEvents {
+    std::vector<hipEvent_t> ev;
+    ~SlotEvents()
+    {
+        for (hipEvent_t e : ev)
+            (void)hipEventDestroy(e);
+    }
+};
+
+} // namespace
+} // namespace rngx
+
+using namespace rngx;
+
+extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, int u32,
+                                   void *dev0, void *dev1, size_t dev_bytes, void *host,
+                                   uint32_t host_slots, rngx_consume_fn consume, void *user,
+                                   void *gen_stream, void *copy_stream)
+{
+    Generator &g = generator();
+    std::lock_guard<std::recursive_mutex> lk(g.mu);
+    clear_error();
+    if (!g.inited)
+        return set_error(RNGX_E_NOINIT, "rngx_stream_to_host called before rngx_init");
+    if (n_steps == 0)
+        return RNGX_OK;
+    const size_t esize = u32 ? 4 : 8;
+    if (iters_per_step == 0)
+        return set_error(RNGX_E_INVAL, "stream_to_host: iters_per_step must be >= 1");
+    if (!dev0 || !dev1 || dev0 == dev1)
+        return set_error(RNGX_E_INVAL, "stream_to_host: need two distinct device buffers");
+    if (reinterpret_cast<uintptr_t>(dev0) % esize || reinterpret_cast<uintptr_t>(dev1) % esize)
+        return set_error(RNGX_E_INVAL, "stream_to_host: device buffers not %zu-byte aligned",
+                         esize);
+    if (!host || host_slots == 0)
+        return set_error(RNGX_E_INVAL, "stream_to_host: need a host buffer with >= 1 slot");
+    const unsigned __int128 step_bytes128 = (unsigned __int128)iters_per_step * g.n * esize;
+    if (step_bytes128 > dev_bytes)
+        return set_error(RNGX_E_INVAL,
+                         "stream_to_host: a step needs %llu bytes but device buffers hold %zu",
+                         (unsigned long long)step_bytes128, dev_bytes);
+    const size_t step_bytes = (size_t)step_bytes128;
+    if ((unsigned __int128)step_bytes * host_slots > (unsigned __int128)SIZE_MAX)
+        return set_error(RNGX_E_INVAL, "stream_to_host: host buffer size overflows size_t");
+    int rc = check_device_locked(g);
+    if (rc)
+        return rc;
+    rc = ensure_pipeline_locked(g);
+    if (rc)
+        return rc;
+    hipStream_t gs = gen_stream ? static_cast<hipStream_t>(gen_stream) : g.pipe_gen;
+    hipStream_t cs = copy_stream ? static_cast<hipStream_t>(copy_stream) : g.pipe_copy;
+    if (gs == cs)
+        return set_error(RNGX_E_INVAL, "stream_to_host: generation and copy streams must differ");
+
+    SlotEvents slots;
+    if (consume) {
+        slots.ev.resize(host_slots, nullptr);
+        for (uint32_t i = 0; i < host_slots; ++i)
+            RNGX_HIP(hipEventCreateWithFlags(&slots.ev[i], hipEventDisableTiming));
+    }
+    void *dev[2] = {dev0, dev1};
+    char *hbase = static_cast<char *>(host);
+
+    auto consume_step = [&](uint64_t k) -> int {
+        const uint32_t slot = (uint32_t)(k % host_slots);
+        RNGX_HIP(hipEventSynchronize(slots.ev[slot]));
+        if (consume(user, k, hbase + (size_t)slot * step_bytes, step_bytes) != 0)
+            return set_error(RNGX_E_ABORTED, "stream_to_host: consumer stopped the stream at step "
+                                             "%llu",
+                             (unsigned long long)k);
+        return RNGX_OK;
+    };
+
+    for (uint64_t k = 0; k < n_steps; ++k) {
+        const uint32_t slot = (uint32_t)(k % host_slots);
+        const int b = (int)(k & 1);
+        if (consume && k >= host_slots) {
+            rc = consume_step(k - host_slots);
+            if (rc) {
+                (void)hipStreamSynchronize(cs);
+                return rc;
+            }
+        }
+        if (k >= 2)
+            RNGX_HIP(hipStreamWaitEvent(gs, g.copy_done[b], 0));
+        rc = generate_locked(g, iters_per_step, dev[b], gs, u32 != 0);
+        if (rc) {
+            (void)hipStreamSynchronize(cs);
+            return rc;
+        }
+        RNGX_HIP(hipEventRecord(g.gen_done[b], gs));
+        RNGX_HIP(hipStreamWaitEvent(cs, g.gen_done[b], 0));
+        const int tok = prof::begin("READ_BUFFER", cs);
+        hipError_t e = hipMemcpyAsync(hbase + (size_t)slot * step_bytes, dev[b], step_bytes,
+                                      hipMemcpyDeviceToHost, cs);
+        prof::end(tok, cs);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(cs);
+            return hip_fail(e, "hipMemcpyAsync (device to host)");
+        }
+        RNGX_HIP(hipEventRecord(g.copy_done[b], cs));
+        if (consume)
+            RNGX_HIP(hipEventRecord(slots.ev[slot], cs));
+    }
+    if (consume) {
+        const uint64_t first = n_steps > host_slots ? n_steps - host_slots : 0;
+        for (uint64_t k = first; k < n_steps; ++k) {
+            rc = consume_step(k);
+            if (rc) {
+                (void)hipStreamSynchronize(cs);
+                return rc;
+            }
+        }
+    }
+    RNGX_HIP(hipStreamSynchronize(cs));
+    return RNGX_OK;
+}

@@ -19,6 +19,10 @@ RNGX_E_NOINIT = -2
 RNGX_E_HIP = -3
 RNGX_E_NOMEM = -4
 RNGX_E_BUSY = -5
+RNGX_E_ABORTED = -6
+
+CONSUME_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                              ctypes.c_size_t)
 
 PROF_NAME = 32
 PROF_MAX_AGG = 16
@@ -73,6 +77,8 @@ _SIGS = {
     "rngx_strerror": ([_int], ctypes.c_char_p),
     "rngx_set_launch": ([_int, ctypes.POINTER(Launch)], _int),
     "rngx_get_launch": ([_int, ctypes.POINTER(Launch)], _int),
+    "rngx_stream_to_host": ([_u32, _u32, _int, _p, _p, ctypes.c_size_t, _p, _u32, CONSUME_FN,
+                             _p, _p, _p], _int),
     "rngx_profile_start": ([], _int),
     "rngx_profile_stop": ([], _int),
     "rngx_profile_enable": ([_int], _int),
@@ -165,6 +171,39 @@ def generate_ptr(n_iters: int, ptr: int, stream: int = 0, u32: bool = False) -> 
     """Raw call (returns the status instead of raising); for ABI tests."""
     f = lib().rngx_generate_u32 if u32 else lib().rngx_generate
     return f(n_iters, ptr, stream)
+
+
+def stream_to_host(n_steps: int, iters_per_step: int, dev0, dev1, host, host_slots: int,
+                   consume=None, u32: bool = False, gen_stream=None, copy_stream=None):
+    """Stream n_steps * iters_per_step iterations to `host` (a pinned CPU
+    tensor of host_slots slots) through device buffers dev0/dev1, generation
+    and copies overlapped on two streams. `consume(step, array)` (optional)
+    receives each step as a numpy view of its host slot, in order; returning
+    a true value stops the stream (raises RngxError with RNGX_E_ABORTED)."""
+    import numpy as np
+    n = info()[1]
+    esize = 4 if u32 else 8
+    step_elems = iters_per_step * n
+    for d in (dev0, dev1):
+        _device_buffer(d, esize, step_elems)
+    if host.is_cuda or not host.is_contiguous() or host.element_size() != esize:
+        raise TypeError("host must be a contiguous CPU tensor of %d-byte integers" % esize)
+    if host.numel() < step_elems * host_slots:
+        raise ValueError("host holds %d elements, %d needed" % (host.numel(), step_elems * host_slots))
+    dev_bytes = min(dev0.numel(), dev1.numel()) * esize
+    cb = CONSUME_FN()
+    if consume is not None:
+        npdt = np.uint32 if u32 else np.uint64
+
+        def _cb(user, step, ptr, nbytes):
+            arr = np.ctypeslib.as_array((ctypes.c_uint8 * nbytes).from_address(ptr)).view(npdt)
+            return 1 if consume(step, arr) else 0
+        cb = CONSUME_FN(_cb)
+    gs = stream_handle(gen_stream) if gen_stream is not None else 0
+    cs = stream_handle(copy_stream) if copy_stream is not None else 0
+    _check(lib().rngx_stream_to_host(n_steps, iters_per_step, int(u32), dev0.data_ptr(),
+                                     dev1.data_ptr(), dev_bytes, host.data_ptr(), host_slots,
+                                     cb, None, gs, cs))
 
 
 def shutdown():

@@ -1,0 +1,156 @@
+"""GPU parity of the two-stream device-to-host pipeline against the oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1609_01257_amd import inputs, rngx
+
+pytestmark = pytest.mark.gpu
+
+
+def _buffers(n, R, slots, u32=False):
+    dt = torch.int32 if u32 else torch.int64
+    dev0 = torch.empty(R * n, dtype=dt, device="cuda")
+    dev1 = torch.empty(R * n, dtype=dt, device="cuda")
+    host = torch.zeros(slots * R * n, dtype=dt, pin_memory=True)
+    return dev0, dev1, host
+
+
+@pytest.mark.parametrize("u32", [False, True])
+@pytest.mark.parametrize("n,R,steps", [(1, 1, 5), (4099, 1, 9), (65537, 3, 4), (1 << 16, 2, 7)])
+def test_every_step_to_its_own_slot(oracle, n, R, steps, u32):
+    seed = 0 if n == 4099 else 17
+    rngx.init(seed, n)
+    dev0, dev1, host = _buffers(n, R, steps, u32)
+    rngx.stream_to_host(steps, R, dev0, dev1, host, steps, u32=u32)
+    got = host.numpy().view(np.uint32 if u32 else np.uint64).reshape(steps * R, n)
+    exp = (oracle.generate_u32 if u32 else oracle.generate)(seed, n, steps * R)
+    assert np.array_equal(got, exp)
+    assert rngx.info()[2] == steps * R
+
+
+def test_consumer_sees_steps_in_order_with_two_slots(oracle):
+    seed, n, R, steps = 42, 10007, 2, 11
+    rngx.init(seed, n)
+    dev0, dev1, host = _buffers(n, R, 2)
+    seen = []
+
+    def consume(step, arr):
+        seen.append((step, arr.copy()))
+        return False
+    rngx.stream_to_host(steps, R, dev0, dev1, host, 2, consume=consume)
+    exp = oracle.generate(seed, n, steps * R)
+    assert [s for s, _ in seen] == list(range(steps))
+    for s, arr in seen:
+        assert np.array_equal(arr.reshape(R, n), exp[s * R:(s + 1) * R])
+
+
+def test_stream_continues_cursor_of_plain_calls(oracle):
+    seed, n = 5, 3001
+    rngx.init(seed, n)
+    pre = torch.empty(4 * n, dtype=torch.int64, device="cuda")
+    rngx.generate(4, pre)
+    dev0, dev1, host = _buffers(n, 1, 6)
+    rngx.stream_to_host(6, 1, dev0, dev1, host, 6)
+    exp = oracle.generate(seed, n, 10)
+    assert np.array_equal(host.numpy().view(np.uint64).reshape(6, n), exp[4:])
+
+
+def test_consumer_abort_stops_and_reports(oracle):
+    seed, n = 3, 2048
+    rngx.init(seed, n)
+    dev0, dev1, host = _buffers(n, 1, 2)
+    seen = []
+
+    def consume(step, arr):
+        seen.append(step)
+        return step == 3
+    with pytest.raises(rngx.RngxError) as ei:
+        rngx.stream_to_host(20, 1, dev0, dev1, host, 2, consume=consume)
+    assert ei.value.code == rngx.RNGX_E_ABORTED
+    assert seen == [0, 1, 2, 3]
+    # Steps generated before the stop advanced the cursor; the generator
+    # continues from there.
+    c = rngx.info()[2]
+    assert 4 <= c <= 6
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    rngx.generate(1, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle.generate(seed, n, 1, cursor=c)[0])
+
+
+def test_stream_argument_errors():
+    rngx.init(0, 1024)
+    dev0, dev1, host = _buffers(1024, 1, 2)
+    L = rngx.lib()
+    cb = rngx.CONSUME_FN()
+    ok = (4, 1, 0, dev0.data_ptr(), dev1.data_ptr(), 8 * 1024, host.data_ptr(), 2, cb, None, 0, 0)
+    assert L.rngx_stream_to_host(*ok) == rngx.RNGX_OK
+    bad = [
+        (4, 0) + ok[2:],                                         # iters_per_step 0
+        ok[:3] + (0,) + ok[4:],                                   # NULL dev0
+        ok[:4] + (dev0.data_ptr(),) + ok[5:],                     # same buffers
+        ok[:5] + (8 * 1023,) + ok[6:],                            # step too large
+        ok[:6] + (None,) + ok[7:],                                # NULL host
+        ok[:7] + (0,) + ok[8:],                                   # zero slots
+        ok[:3] + (dev0.data_ptr() + 4,) + ok[4:],                 # misaligned
+    ]
+    for args in bad:
+        assert L.rngx_stream_to_host(*args) == rngx.RNGX_E_INVAL, args
+    s = torch.cuda.Stream()
+    same = ok[:10] + (s.cuda_stream, s.cuda_stream)
+    assert L.rngx_stream_to_host(*same) == rngx.RNGX_E_INVAL
+    assert L.rngx_stream_to_host(0, 1, 0, None, None, 0, None, 0, cb, None, 0, 0) == rngx.RNGX_OK
+
+
+def test_profile_of_a_stream_has_fig3_rows():
+    n, steps = 1 << 20, 16
+    rngx.init(0, n)
+    dev0, dev1, host = _buffers(n, 1, 2)
+    rngx.stream_to_host(steps, 1, dev0, dev1, host, 2)
+    st = rngx.profile_stats()
+    counts = {name: c for name, c, _, _ in st["agg"]}
+    assert counts == {"INIT_KERNEL": 1, "RNG_KERNEL": steps, "READ_BUFFER": steps}
+    assert st["eff_s"] <= st["total_s"] and st["eff_s"] > 0
+    assert 0 < st["device_pct"] <= 100.0 + 1e-6
+    for a, b, ov in st["overlaps"]:
+        assert {a, b} <= {"INIT_KERNEL", "RNG_KERNEL", "READ_BUFFER"} and ov > 0
+    ev = rngx.profile_events()
+    queues = {name: {q for nm, q, _, _ in ev if nm == name} for name in counts}
+    assert len(queues["READ_BUFFER"]) == 1 and queues["READ_BUFFER"] != queues["RNG_KERNEL"]
+    # Copies of one stream are in order and never overlap each other.
+    reads = sorted((s, e) for nm, _, s, e in ev if nm == "READ_BUFFER")
+    assert all(reads[i][1] <= reads[i + 1][0] for i in range(len(reads) - 1))
+    text = rngx.profile()
+    assert "READ_BUFFER" in text and "Time spent in device" in text
+
+
+def test_paper_shaped_streaming_sampled(oracle):
+    """4,194,304 work-items, seed 42, 2,000 iterations (32 MiB each) through
+    two device buffers and two pinned host slots; every step is checked at
+    sampled positions against the oracle, one value at a time."""
+    cfg = inputs.STREAMING
+    seed, n, steps = cfg["seed"], cfg["n"], cfg["iters"]
+    rngx.init(seed, n)
+    dev0, dev1, host = _buffers(n, 1, 2)
+    rng = np.random.default_rng(2000)
+    gids = np.concatenate([[0, n - 1], rng.integers(0, n, 14)])
+    # Expected values, computed by stepping each sampled stream in the oracle.
+    exp = np.empty((steps, len(gids)), dtype=np.uint64)
+    for j, g in enumerate(gids):
+        x = oracle.init_state(seed, int(g))
+        for k in range(steps):
+            exp[k, j] = x
+            x = oracle.rng_step(x)
+    bad = []
+
+    def consume(step, arr):
+        if not np.array_equal(arr[gids], exp[step]):
+            bad.append(step)
+        return False
+    rngx.stream_to_host(steps, 1, dev0, dev1, host, 2, consume=consume)
+    assert bad == []
+    st = rngx.profile_stats()
+    counts = {name: c for name, c, _, _ in st["agg"]}
+    assert counts["READ_BUFFER"] == steps and counts["RNG_KERNEL"] == steps
