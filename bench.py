@@ -153,6 +153,52 @@ def streaming(torch, rngx):
     }
 
 
+def batched(torch, rngx, steps):
+    """Batched ragged streams: 4,096 streams with seeds from default_rng(1609),
+    lengths log-uniform in [2^10, 2^24), one persistent launch per step,
+    replayed from a HIP graph, launch configuration from the autotuner;
+    compared with the plain kernel writing the same number of bytes."""
+    from paper_1609_01257_amd import inputs
+    r = inputs.batched_requests()
+    reqs = rngx.make_reqs(r.seeds, r.gids, r.offsets, r.lengths)
+    out = torch.empty(r.total, dtype=torch.int64, device="cuda")
+    rngx.set_batch_cfg(256, 4, 0, True)
+    tune = rngx.autotune_batch(reqs, out, reps=2)
+    log("autotune best:", tune["best"], "%.3f ms" % tune["best_ms"])
+    rngx.generate_batch(reqs, out)
+    torch.cuda.synchronize()
+    rngx.profile_start()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rngx.generate_batch(reqs, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = rngx.profile_stats()
+    avg, count = kernel_avg_s(st, "BATCH_KERNEL")
+    del out
+    torch.cuda.empty_cache()
+    nbytes = 8 * r.total
+    # Plain generator at equal output bytes: 2^24 streams x ceil(total / 2^24) iterations.
+    n_eq = 1 << 24
+    it_eq = -(-r.total // n_eq)
+    plain = plain_run(torch, rngx, 1, n_eq, it_eq, False, 1, steps)
+    res = {
+        "workload": "4,096 streams, seeds from default_rng(1609), lengths floor(2^U[10,24)), "
+                    "%d values (%.2f GB) per launch" % (r.total, nbytes / 1e9),
+        "out_gbs": round(nbytes * steps / (t1 - t0) / 1e9, 1),
+        "kernel_avg_ms": round(avg * 1e3, 4),
+        "kernel_gbs": round(nbytes / avg / 1e9, 1),
+        "frac_hbm": round(nbytes / avg / 1e9 / HBM_PEAK_GBS, 4),
+        "autotune_best": tune["best"],
+        "autotune_candidates": len(tune["tried"]),
+        "plain_equal_bytes": {"n_states": n_eq, "iters": it_eq,
+                              "kernel_gbs": round(plain["kernel_gbs"], 1),
+                              "out_gbs": round(plain["out_gbs"], 1)},
+    }
+    res["batched_vs_plain"] = round(res["kernel_gbs"] / plain["kernel_gbs"], 4)
+    return res
+
+
 def cpu_baseline(n_total, iters):
     """The CPU oracle, single-threaded, on the first 2^20 work-items of the
     workload (all iterations)."""
@@ -238,6 +284,9 @@ def main():
                          "frac_hbm": round(h32["kernel_gbs"] / HBM_PEAK_GBS, 4)}
         if not args.no_sweep:
             result["sweep"] = sweep(torch, rngx, 3)
+        log("batched ragged streams")
+        result["batched"] = batched(torch, rngx, max(3, args.steps // 4))
+        log("batched:", result["batched"])
         log("streaming (two-stream device-to-host pipeline)")
         result["streaming"] = streaming(torch, rngx)
         log("streaming:", result["streaming"])

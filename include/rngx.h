@@ -142,7 +142,8 @@ typedef int (*rngx_consume_fn)(void *user, uint64_t step, const void *values, si
  * waits only for the copy of step k - 2; step k's copy waits for its
  * generation. Kernels are profiled as RNG_KERNEL and copies as READ_BUFFER.
  * host: host_slots consecutive slots of one step each; page-locked memory
- *       (hipHostMalloc, or torch pin_memory) makes the copies asynchronous.
+ *       (hipHostMalloc, or torch pin_memory) makes the copies asynchronous
+ *       and lets the copy kernel write it directly (see rngx_set_copy_mode).
  * consume: optional (NULL = no host consumer, as when the paper's output is
  *       sent to the null device); with it, a slot is refilled only after the
  *       consumer returned for the step it held.
@@ -157,6 +158,102 @@ int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, int u32, void
                         void *dev1, size_t dev_bytes, void *host, uint32_t host_slots,
                         rngx_consume_fn consume, void *user, void *gen_stream,
                         void *copy_stream);
+
+/* How rngx_stream_to_host moves each step to the host:
+ * RNGX_COPY_KERNEL (default): the library's copy kernel stores straight into
+ *   the page-locked host buffer through its device-mapped address (falls
+ *   back to RNGX_COPY_RUNTIME if `host` is not page-locked memory);
+ * RNGX_COPY_RUNTIME: hipMemcpyAsync on the copy stream.
+ * blocks: workgroups of 256 lanes for the copy kernel (1..65536).
+ * Errors: RNGX_E_INVAL for an unknown mode or blocks out of range. */
+#define RNGX_COPY_KERNEL 0
+#define RNGX_COPY_RUNTIME 1
+int rngx_set_copy_mode(int mode, uint32_t blocks);
+int rngx_get_copy_mode(int *mode, uint32_t *blocks);
+
+/* ------------------------------------------------------------------------ */
+/* Batched ragged streams                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* One request: `length` consecutive values of the stream of work-item `gid`
+ * under `seed`, starting at value number `offset`, i.e.
+ * V(seed, gid, offset + t) for t < length. 32 bytes, host memory. */
+typedef struct rngx_req {
+    uint64_t seed;
+    uint64_t offset;
+    uint64_t length;
+    uint32_t gid;
+    uint32_t reserved; /* must be 0 */
+} rngx_req;
+
+/* Generate m independent streams of uneven lengths in one launch:
+ *     out[base_j + t] = V(seed_j, gid_j, offset_j + t),  t < length_j,
+ *     base_j = length_0 + ... + length_{j-1}  (packed in request order).
+ * The paper's init and rng kernels give one uniform grid of streams; here
+ * every request is its own seeded stream, started at any value number by
+ * GF(2) jump-ahead (so long streams split across many wavefronts), all in
+ * one persistent kernel launch, replayed from a captured HIP graph when the
+ * graph mode of the batch configuration is on. Independent of rngx_init:
+ * the plain generator's state and cursor are untouched.
+ * reqs: m requests in host memory (zero-length requests produce nothing).
+ * out:  device memory of out_cap uint64 values, 16-byte aligned.
+ * Errors: RNGX_E_INVAL (NULL reqs with m > 0, NULL or misaligned out, a
+ * nonzero reserved field, total length above out_cap or overflowing);
+ * RNGX_E_NOMEM; RNGX_E_HIP. */
+int rngx_generate_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_t out_cap,
+                        void *stream);
+
+/* Launch configuration of the batched kernel.
+ * values_per_lane: S, values each lane produces per work item (64, 128,
+ *   256, 512 or 1024); a work item is a tile of 64 * S output values.
+ * waves_per_block: 1..4; blocks: 1..65536 (the persistent grid);
+ * use_graph: 1 to capture the table upload and the launch in a HIP graph
+ *   once and replay it, 0 to launch directly.
+ * The output never depends on the configuration. */
+typedef struct rngx_batch_cfg {
+    uint32_t values_per_lane;
+    uint32_t waves_per_block;
+    uint32_t blocks;
+    uint32_t use_graph;
+} rngx_batch_cfg;
+
+int rngx_set_batch_cfg(const rngx_batch_cfg *cfg);
+int rngx_get_batch_cfg(rngx_batch_cfg *cfg);
+
+#define RNGX_TUNE_MAX 64
+typedef struct rngx_tune_entry {
+    rngx_batch_cfg cfg;
+    double ms; /* mean kernel time over the timed repetitions */
+} rngx_tune_entry;
+typedef struct rngx_tune_result {
+    rngx_batch_cfg best;
+    double best_ms;
+    double best_gbs; /* output bytes / best_ms */
+    uint32_t n_tried;
+    uint32_t reserved;
+    rngx_tune_entry tried[RNGX_TUNE_MAX];
+} rngx_tune_result;
+
+/* Autotuner (the paper's work-size suggestion, Section 6.1, made empirical):
+ * time every candidate launch configuration (values_per_lane x
+ * waves_per_block x grid size) on this request table with HIP events, check
+ * that every candidate's output has the same checksum, keep the fastest as
+ * the batch configuration, and report all of them. `out` receives the
+ * requests' output. reps: timed launches per candidate (>= 1).
+ * Errors: as rngx_generate_batch; RNGX_E_HIP if two candidates disagree. */
+int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_t out_cap,
+                        uint32_t reps, void *stream, rngx_tune_result *result);
+
+/* Order-sensitive checksum sum_i data[i] * (2 i + 1) mod 2^64 of n device
+ * values, computed on the device; waits for `stream` and writes *result.
+ * Errors: RNGX_E_INVAL (NULL result, NULL data with n > 0); RNGX_E_HIP. */
+int rngx_checksum(const uint64_t *data, uint64_t n, void *stream, uint64_t *result);
+
+/* Host-side helpers of the same definitions (no GPU needed):
+ * rngx_initial_state: *out = H(seed, gid) (Listing S4 with the seed folded in);
+ * rngx_jump_ahead:    *out = XS^k(state), by GF(2) jump-ahead. */
+int rngx_initial_state(uint64_t seed, uint32_t gid, uint64_t *out);
+int rngx_jump_ahead(uint64_t state, uint64_t k, uint64_t *out);
 
 /* ------------------------------------------------------------------------ */
 /* Event profiling (the profiler module, Section 4.3; summary of Fig. 3)     */

@@ -1,0 +1,452 @@
+// Host side of the batched path: request packing, work-item numbering,
+// HIP-graph capture and replay, the autotuner, and the device checksum.
+//
+// A BatchSlot owns one page-locked staging buffer and one device table
+// (a BatchDesc followed by the packed BatchReq array). A batch is staged on
+// the host, then one HIP graph copies the table to the device and launches
+// the persistent kernel; the graph is captured once per (capacity, launch
+// configuration) and replayed for every later batch, because the kernel
+// reads everything that changes from the device table. Before a slot's
+// staging buffer is rewritten, the slot's previous batch must have finished
+// (its `done` event).
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+namespace rngx {
+
+namespace {
+
+const uint32_t kValuesPerLane[5] = {64, 128, 256, 512, 1024};
+
+int s_index(uint32_t s)
+{
+    for (int i = 0; i < 5; ++i)
+        if (kValuesPerLane[i] == s)
+            return i;
+    return -1;
+}
+
+struct BatchGlobals {
+    std::mutex mu;
+    int device = -1;
+    int n_cus = 0;
+    uint64_t *d_pow2 = nullptr;   // 64 matrices x 64 rows
+    uint64_t *d_rows_s = nullptr; // T^S rows for each allowed S (5 x 64)
+    uint64_t *d_acc = nullptr;    // checksum accumulator
+    uint64_t *h_acc = nullptr;    // page-locked copy of it
+    rngx_batch_cfg cfg{256, 4, 0, 1};
+    BatchSlot api_slot;
+};
+
+BatchGlobals &G()
+{
+    static BatchGlobals *g = new BatchGlobals;
+    return *g;
+}
+
+void free_slot(BatchSlot &s)
+{
+    if (s.done)
+        (void)hipEventSynchronize(s.done);
+    if (s.exec)
+        (void)hipGraphExecDestroy(s.exec);
+    if (s.staging)
+        (void)hipHostFree(s.staging);
+    if (s.devtab)
+        (void)hipFree(s.devtab);
+    if (s.done)
+        (void)hipEventDestroy(s.done);
+    if (s.cap_stream)
+        (void)hipStreamDestroy(s.cap_stream);
+    s = BatchSlot();
+}
+
+} // namespace
+
+int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus)
+{
+    BatchGlobals &g = G();
+    int dev = -1;
+    RNGX_HIP(hipGetDevice(&dev));
+    if (g.device != dev || !g.d_pow2) {
+        if (g.d_pow2)
+            (void)hipFree(g.d_pow2);
+        if (g.d_rows_s)
+            (void)hipFree(g.d_rows_s);
+        if (g.d_acc)
+            (void)hipFree(g.d_acc);
+        if (g.h_acc)
+            (void)hipHostFree(g.h_acc);
+        g.d_pow2 = g.d_rows_s = g.d_acc = g.h_acc = nullptr;
+        std::vector<uint64_t> rows(5 * 64);
+        for (int i = 0; i < 5; ++i)
+            power_rows(kValuesPerLane[i], rows.data() + 64 * i);
+        RNGX_HIP(hipMalloc(&g.d_pow2, 64 * 64 * sizeof(uint64_t)));
+        RNGX_HIP(hipMalloc(&g.d_rows_s, rows.size() * sizeof(uint64_t)));
+        RNGX_HIP(hipMalloc(&g.d_acc, sizeof(uint64_t)));
+        RNGX_HIP(hipHostMalloc(&g.h_acc, sizeof(uint64_t), hipHostMallocDefault));
+        RNGX_HIP(hipMemcpy(g.d_pow2, jump_tables(), 64 * 64 * sizeof(uint64_t),
+                           hipMemcpyHostToDevice));
+        RNGX_HIP(hipMemcpy(g.d_rows_s, rows.data(), rows.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice));
+        RNGX_HIP(hipDeviceGetAttribute(&g.n_cus, hipDeviceAttributeMultiprocessorCount, dev));
+        g.device = dev;
+    }
+    if (pow2)
+        *pow2 = g.d_pow2;
+    if (rows_s_all)
+        *rows_s_all = g.d_rows_s;
+    if (n_cus)
+        *n_cus = g.n_cus;
+    return RNGX_OK;
+}
+
+rngx_batch_cfg resolved_cfg(const rngx_batch_cfg &c, int n_cus)
+{
+    rngx_batch_cfg r = c;
+    if (r.blocks == 0) // 16 waves per compute unit
+        r.blocks = (uint32_t)std::max(1, n_cus * 16 / (int)r.waves_per_block);
+    return r;
+}
+
+int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out,
+                uint64_t out_cap, uint32_t values_per_lane, uint64_t *total_out)
+{
+    if (m && !reqs)
+        return set_error(RNGX_E_INVAL, "batch: reqs is NULL");
+    unsigned __int128 total = 0;
+    uint32_t nonzero = 0;
+    for (uint32_t j = 0; j < m; ++j) {
+        if (reqs[j].reserved)
+            return set_error(RNGX_E_INVAL, "batch: request %u has a nonzero reserved field", j);
+        total += reqs[j].length;
+        nonzero += reqs[j].length != 0;
+    }
+    if (total > (unsigned __int128)UINT64_MAX / 8)
+        return set_error(RNGX_E_INVAL, "batch: total length overflows");
+    if ((uint64_t)total > out_cap)
+        return set_error(RNGX_E_INVAL, "batch: requests need %llu values but out holds %llu",
+                         (unsigned long long)total, (unsigned long long)out_cap);
+    if (total && !out)
+        return set_error(RNGX_E_INVAL, "batch: out is NULL");
+    if (total && (reinterpret_cast<uintptr_t>(out) & 15u))
+        return set_error(RNGX_E_INVAL, "batch: out is not 16-byte aligned");
+    if (total == 0) {
+        *total_out = 0;
+        return RNGX_OK;
+    }
+
+    int rc = RNGX_OK;
+    // Grow the slot to a power-of-two capacity (>= 64 requests).
+    if (nonzero > slot.capacity || !slot.staging) {
+        uint32_t cap = 64;
+        while (cap < nonzero)
+            cap <<= 1;
+        if (slot.done)
+            RNGX_HIP(hipEventSynchronize(slot.done));
+        if (slot.exec) {
+            (void)hipGraphExecDestroy(slot.exec);
+            slot.exec = nullptr;
+        }
+        if (slot.staging)
+            (void)hipHostFree(slot.staging);
+        if (slot.devtab)
+            (void)hipFree(slot.devtab);
+        slot.staging = slot.devtab = nullptr;
+        slot.capacity = 0;
+        const size_t bytes = sizeof(BatchDesc) + (size_t)cap * sizeof(BatchReq);
+        hipError_t e = hipHostMalloc(&slot.staging, bytes, hipHostMallocDefault);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipHostMalloc (batch staging)");
+        e = hipMalloc(&slot.devtab, bytes);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMalloc (batch table)");
+        slot.capacity = cap;
+    }
+    if (!slot.done)
+        RNGX_HIP(hipEventCreateWithFlags(&slot.done, hipEventDisableTiming));
+    // The slot's previous batch must have read its table before we rewrite it.
+    RNGX_HIP(hipEventSynchronize(slot.done));
+
+    const uint64_t C = 64ull * values_per_lane;
+    BatchDesc *desc = static_cast<BatchDesc *>(slot.staging);
+    BatchReq *tab = reinterpret_cast<BatchReq *>(desc + 1);
+    uint64_t base = 0, items = 0;
+    uint32_t k = 0;
+    for (uint32_t j = 0; j < m; ++j) {
+        const uint64_t len = reqs[j].length;
+        if (len) {
+            BatchReq &r = tab[k++];
+            const SeedMix mix = seed_mix(reqs[j].seed);
+            r.offset = reqs[j].offset;
+            r.length = len;
+            r.base = base;
+            r.item_begin = items;
+            r.first_tile = base / C;
+            r.gid = reqs[j].gid;
+            r.mix_low = mix.mix_low;
+            r.mix_high = mix.mix_high;
+            r.zero_fix = mix.zero_fix;
+            r.reserved = 0;
+            items += (base + len - 1) / C - r.first_tile + 1;
+        }
+        base += len;
+    }
+    std::memset(desc, 0, sizeof *desc);
+    desc->out = out;
+    desc->reqs = reinterpret_cast<const BatchReq *>(static_cast<char *>(slot.devtab) +
+                                                    sizeof(BatchDesc));
+    desc->n_items = items;
+    desc->m = k;
+    slot.m_staged = k;
+    slot.n_items = items;
+    *total_out = base;
+    return rc;
+}
+
+int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stream)
+{
+    const uint64_t *pow2 = nullptr, *rows_all = nullptr;
+    int n_cus = 0;
+    int rc = batch_tables_locked(&pow2, &rows_all, &n_cus);
+    if (rc)
+        return rc;
+    const rngx_batch_cfg cfg = resolved_cfg(cfg_in, n_cus);
+    const uint64_t *rows_s = rows_all + 64 * s_index(cfg.values_per_lane);
+    const BatchDesc *ddesc = static_cast<const BatchDesc *>(slot.devtab);
+    const int tok = prof::begin("BATCH_KERNEL", stream);
+    if (cfg.use_graph) {
+        const bool same = slot.exec && slot.exec_cfg.values_per_lane == cfg.values_per_lane &&
+                          slot.exec_cfg.waves_per_block == cfg.waves_per_block &&
+                          slot.exec_cfg.blocks == cfg.blocks;
+        if (!same) {
+            if (slot.exec) {
+                (void)hipGraphExecDestroy(slot.exec);
+                slot.exec = nullptr;
+            }
+            if (!slot.cap_stream)
+                RNGX_HIP(hipStreamCreateWithFlags(&slot.cap_stream, hipStreamNonBlocking));
+            const size_t bytes = sizeof(BatchDesc) + (size_t)slot.capacity * sizeof(BatchReq);
+            RNGX_HIP(hipStreamBeginCapture(slot.cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e1 = hipMemcpyAsync(slot.devtab, slot.staging, bytes,
+                                           hipMemcpyHostToDevice, slot.cap_stream);
+            hipError_t e2 = launch_batch(cfg, ddesc, pow2, rows_s, slot.cap_stream);
+            hipGraph_t graph = nullptr;
+            hipError_t e3 = hipStreamEndCapture(slot.cap_stream, &graph);
+            if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+                if (graph)
+                    (void)hipGraphDestroy(graph);
+                return hip_fail(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3),
+                                "batch graph capture");
+            }
+            hipError_t e4 = hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e4 != hipSuccess) {
+                slot.exec = nullptr;
+                return hip_fail(e4, "hipGraphInstantiate (batch)");
+            }
+            slot.exec_cfg = cfg;
+        }
+        RNGX_HIP(hipGraphLaunch(slot.exec, stream));
+    } else {
+        const size_t bytes = sizeof(BatchDesc) + (size_t)slot.m_staged * sizeof(BatchReq);
+        RNGX_HIP(hipMemcpyAsync(slot.devtab, slot.staging, bytes, hipMemcpyHostToDevice, stream));
+        hipError_t e = launch_batch(cfg, ddesc, pow2, rows_s, stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "batch kernel launch");
+    }
+    prof::end(tok, stream);
+    RNGX_HIP(hipEventRecord(slot.done, stream));
+    return RNGX_OK;
+}
+
+void release_slot(BatchSlot &slot) { free_slot(slot); }
+
+rngx_batch_cfg current_batch_cfg()
+{
+    std::lock_guard<std::mutex> lk(G().mu);
+    return G().cfg;
+}
+
+void release_batch()
+{
+    BatchGlobals &g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    free_slot(g.api_slot);
+    if (g.d_pow2)
+        (void)hipFree(g.d_pow2);
+    if (g.d_rows_s)
+        (void)hipFree(g.d_rows_s);
+    if (g.d_acc)
+        (void)hipFree(g.d_acc);
+    if (g.h_acc)
+        (void)hipHostFree(g.h_acc);
+    g.d_pow2 = g.d_rows_s = g.d_acc = g.h_acc = nullptr;
+    g.device = -1;
+}
+
+int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *result)
+{
+    int rc = batch_tables_locked(nullptr, nullptr, nullptr);
+    if (rc)
+        return rc;
+    BatchGlobals &g = G();
+    RNGX_HIP(hipMemsetAsync(g.d_acc, 0, sizeof(uint64_t), s));
+    RNGX_HIP(launch_checksum(data, n, g.d_acc, s));
+    RNGX_HIP(hipMemcpyAsync(g.h_acc, g.d_acc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    RNGX_HIP(hipStreamSynchronize(s));
+    *result = *g.h_acc;
+    return RNGX_OK;
+}
+
+} // namespace rngx
+
+using namespace rngx;
+
+extern "C" int rngx_generate_batch(const rngx_req *reqs, uint32_t m, uint64_t *out,
+                                   uint64_t out_cap, void *stream)
+{
+    BatchGlobals &g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    clear_error();
+    uint64_t total = 0;
+    int rc = batch_stage(g.api_slot, reqs, m, out, out_cap, g.cfg.values_per_lane, &total);
+    if (rc)
+        return rc;
+    if (total == 0)
+        return RNGX_OK;
+    return batch_launch(g.api_slot, g.cfg, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int rngx_set_batch_cfg(const rngx_batch_cfg *cfg)
+{
+    BatchGlobals &g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    clear_error();
+    if (!cfg || !batch_cfg_valid(*cfg))
+        return set_error(RNGX_E_INVAL, "rngx_set_batch_cfg: values_per_lane must be 64, 128, "
+                                       "256, 512 or 1024, waves_per_block 1..4, blocks "
+                                       "0..65536 (0 = 16 waves per compute unit), use_graph 0/1");
+    g.cfg = *cfg;
+    return RNGX_OK;
+}
+
+extern "C" int rngx_get_batch_cfg(rngx_batch_cfg *cfg)
+{
+    BatchGlobals &g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    clear_error();
+    if (!cfg)
+        return set_error(RNGX_E_INVAL, "rngx_get_batch_cfg: NULL");
+    *cfg = g.cfg;
+    return RNGX_OK;
+}
+
+extern "C" int rngx_checksum(const uint64_t *data, uint64_t n, void *stream, uint64_t *result)
+{
+    BatchGlobals &g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    clear_error();
+    if (!result)
+        return set_error(RNGX_E_INVAL, "rngx_checksum: result is NULL");
+    if (n && !data)
+        return set_error(RNGX_E_INVAL, "rngx_checksum: data is NULL");
+    return checksum_locked(data, n, static_cast<hipStream_t>(stream), result);
+}
+
+extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *out,
+                                   uint64_t out_cap, uint32_t reps, void *stream,
+                                   rngx_tune_result *result)
+{
+    BatchGlobals &g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    clear_error();
+    if (!result)
+        return set_error(RNGX_E_INVAL, "rngx_autotune_batch: result is NULL");
+    if (reps == 0)
+        return set_error(RNGX_E_INVAL, "rngx_autotune_batch: reps must be >= 1");
+    int n_cus = 0;
+    int rc = batch_tables_locked(nullptr, nullptr, &n_cus);
+    if (rc)
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::memset(result, 0, sizeof *result);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RNGX_HIP(hipEventCreate(&e0));
+    RNGX_HIP(hipEventCreate(&e1));
+    struct Events {
+        hipEvent_t a, b;
+        ~Events()
+        {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+
+    uint64_t ref_sum = 0, total = 0;
+    bool have_ref = false;
+    double best = 1e300;
+    const uint32_t wpbs[3] = {1, 2, 4};
+    const uint32_t waves_per_cu[3] = {4, 8, 16};
+    for (uint32_t si = 0; si < 5; ++si) {
+        for (uint32_t wi = 0; wi < 3; ++wi) {
+            for (uint32_t oi = 0; oi < 3; ++oi) {
+                rngx_batch_cfg c;
+                c.values_per_lane = kValuesPerLane[si];
+                c.waves_per_block = wpbs[wi];
+                c.blocks = (uint32_t)std::max(1, n_cus * (int)waves_per_cu[oi] / (int)wpbs[wi]);
+                c.use_graph = g.cfg.use_graph;
+                rc = batch_stage(g.api_slot, reqs, m, out, out_cap, c.values_per_lane, &total);
+                if (rc)
+                    return rc;
+                if (total == 0)
+                    return set_error(RNGX_E_INVAL, "rngx_autotune_batch: no values requested");
+                rc = batch_launch(g.api_slot, c, s); // warm-up (and graph capture)
+                if (rc)
+                    return rc;
+                uint64_t sum = 0;
+                rc = checksum_locked(out, total, s, &sum);
+                if (rc)
+                    return rc;
+                if (!have_ref) {
+                    ref_sum = sum;
+                    have_ref = true;
+                } else if (sum != ref_sum) {
+                    return set_error(RNGX_E_HIP,
+                                     "autotune: configuration (S=%u, waves/block=%u, blocks=%u) "
+                                     "produced a different output",
+                                     c.values_per_lane, c.waves_per_block, c.blocks);
+                }
+                RNGX_HIP(hipEventRecord(e0, s));
+                for (uint32_t r = 0; r < reps; ++r) {
+                    rc = batch_launch(g.api_slot, c, s);
+                    if (rc)
+                        return rc;
+                }
+                RNGX_HIP(hipEventRecord(e1, s));
+                RNGX_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                RNGX_HIP(hipEventElapsedTime(&ms, e0, e1));
+                const double mean = (double)ms / reps;
+                if (result->n_tried < RNGX_TUNE_MAX) {
+                    result->tried[result->n_tried].cfg = c;
+                    result->tried[result->n_tried].ms = mean;
+                }
+                ++result->n_tried;
+                if (mean < best) {
+                    best = mean;
+                    result->best = c;
+                }
+            }
+        }
+    }
+    result->best_ms = best;
+    result->best_gbs = (double)total * 8.0 / (best * 1e-3) / 1e9;
+    g.cfg = result->best;
+    return RNGX_OK;
+}

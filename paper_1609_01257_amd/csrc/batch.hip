@@ -1,0 +1,228 @@
+// Batched ragged streams in one persistent launch.
+//
+// Request j names one stream (seed_j, gid_j) and asks for length_j values
+// starting at value number offset_j; outputs are packed one request after
+// another:  out[base_j + t] = V(seed_j, gid_j, offset_j + t).
+//
+// Work decomposition. The packed output index space is cut into tiles of
+// C = 64 * S values aligned to multiples of C. A work item is one (request,
+// tile) pair whose ranges intersect; items are numbered request by request,
+// so item -> request is a binary search over the requests' first item
+// numbers. A fixed grid of wavefronts walks the items with a static stride
+// (every item costs about the same), and every wave leaves the loop when the
+// items run out.
+//
+// Per item, lane l produces the S values of the tile's l-th sub-range. Its
+// starting state comes from GF(2) jump-ahead done by the whole wave at once:
+// lane r holds row r of a jump matrix M and M x is one AND, two popcounts
+// and a ballot (x is uniform across the wave). The wave first jumps from
+// the stream's initial state to the tile's first position with the
+// T^(2^b) tables, then walks lane by lane with T^S, depositing each
+// lane's start. Each lane then emits 16 values per round into its own LDS
+// row (one 128-byte line), and the wave writes the 64 lines back with
+// 16-byte stores, 8 lanes per line, so every store instruction covers whole
+// lines. LDS and cross-lane operations appear only for this bookkeeping.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace rngx {
+
+namespace {
+
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+constexpr int ROUND = 16;        // values per lane per LDS round (one 128-byte line)
+constexpr int LDS_ROW = 18;      // u64 per LDS row: 16 values + 2 padding (bank spread)
+constexpr int MAX_WAVES_PER_BLOCK = 4;
+
+__device__ __forceinline__ uint64_t wave_matvec(uint64_t row, uint64_t x)
+{
+    const uint64_t t = row & x;
+    const uint32_t pc = __builtin_popcount((uint32_t)t) + __builtin_popcount((uint32_t)(t >> 32));
+    return __ballot((pc & 1u) != 0u);
+}
+
+// T^k x for a wave-uniform k and x, with pow2 = 64 matrices of 64 rows.
+__device__ __forceinline__ uint64_t wave_jump(const uint64_t *__restrict__ pow2, uint32_t lane,
+                                              uint64_t x, uint64_t k)
+{
+    while (k) {
+        const int b = __builtin_ctzll(k);
+        x = wave_matvec(pow2[64 * b + lane], x);
+        k &= k - 1;
+    }
+    return x;
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict__ desc,
+                                                    const uint64_t *__restrict__ pow2,
+                                                    const uint64_t *__restrict__ rows_s)
+{
+    constexpr uint64_t C = 64ull * S;
+    extern __shared__ uint64_t lds_dyn[]; // 64 * LDS_ROW u64 per wave
+    const uint32_t lane = threadIdx.x & 63u;
+    // Wave index, made provably uniform so item bookkeeping runs on the
+    // scalar unit and the request table is read with scalar loads.
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint64_t *lds = lds_dyn + (size_t)wid * 64 * LDS_ROW;
+
+    const uint64_t n_items = desc->n_items;
+    const uint32_t m = desc->m;
+    const BatchReq *__restrict__ reqs = desc->reqs;
+    uint64_t *__restrict__ out = desc->out;
+    const uint64_t row_s = rows_s[lane];
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+
+    for (uint64_t item = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wid; item < n_items;
+         item += waves) {
+        // Request of this item: the last j with item_begin <= item.
+        uint32_t lo = 0, hi = m;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (reqs[mid].item_begin <= item)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const BatchReq r = reqs[lo];
+        const uint64_t B = r.base, E = r.base + r.length;
+        const uint64_t T0 = (r.first_tile + (item - r.item_begin)) * C;
+        const uint64_t q0 = T0 > B ? T0 : B;
+
+        // State at q0, then each active lane's first position.
+        SeedMix mix;
+        mix.mix_low = r.mix_low;
+        mix.mix_high = r.mix_high;
+        mix.zero_fix = r.zero_fix;
+        uint64_t cur = wave_jump(pow2, lane, init_state(mix, r.gid), r.offset + (q0 - B));
+        uint64_t curpos = q0;
+        uint64_t x = 0;
+        for (uint32_t l = 0; l < 64; ++l) {
+            const uint64_t ls = T0 + (uint64_t)l * S;
+            const uint64_t p = ls > B ? ls : B;
+            const uint64_t e = (ls + S) < E ? (ls + S) : E;
+            if (p >= e)
+                continue;
+            const uint64_t delta = p - curpos;
+            if (delta == (uint64_t)S)
+                cur = wave_matvec(row_s, cur);
+            else if (delta)
+                cur = wave_jump(pow2, lane, cur, delta);
+            curpos = p;
+            if (lane == l)
+                x = cur;
+        }
+
+        const bool full = T0 >= B && T0 + C <= E;
+        const uint64_t my0 = T0 + (uint64_t)lane * S;
+        for (uint32_t rd = 0; rd < (uint32_t)S / ROUND; ++rd) {
+            const uint64_t p0 = my0 + (uint64_t)rd * ROUND;
+            if (full) {
+#pragma unroll
+                for (int s = 0; s < ROUND; ++s) {
+                    lds[lane * LDS_ROW + s] = x;
+                    x = xs_step(x);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < ROUND; ++s) {
+                    const uint64_t P = p0 + s;
+                    if (P >= B && P < E) {
+                        lds[lane * LDS_ROW + s] = x;
+                        x = xs_step(x);
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t row = 8u * i + (lane >> 3);
+                const uint32_t ch = lane & 7u;
+                const uint64_t P = T0 + (uint64_t)row * S + (uint64_t)rd * ROUND + 2u * ch;
+                const u64x2 v = *reinterpret_cast<const u64x2 *>(&lds[row * LDS_ROW + 2u * ch]);
+                if (full) {
+                    *reinterpret_cast<u64x2 *>(out + P) = v;
+                } else {
+                    const bool v0 = P >= B && P < E;
+                    const bool v1 = P + 1 >= B && P + 1 < E;
+                    if (v0 && v1)
+                        *reinterpret_cast<u64x2 *>(out + P) = v;
+                    else if (v0)
+                        out[P] = v.x;
+                    else if (v1)
+                        out[P + 1] = v.y;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
+template <int S>
+hipError_t launch_batch_s(const BatchDesc *desc, const uint64_t *pow2, const uint64_t *rows_s,
+                          uint32_t blocks, uint32_t waves_per_block, hipStream_t s)
+{
+    const size_t lds_bytes = (size_t)waves_per_block * 64 * LDS_ROW * sizeof(uint64_t);
+    batch_kernel<S><<<dim3(blocks), dim3(64 * waves_per_block), lds_bytes, s>>>(desc, pow2,
+                                                                               rows_s);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void checksum_kernel(const uint64_t *__restrict__ d, uint64_t n,
+                                                       unsigned long long *acc)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long s = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        s += d[i] * (2 * i + 1);
+    for (int off = 32; off > 0; off >>= 1)
+        s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63u) == 0)
+        atomicAdd(acc, s);
+}
+
+} // namespace
+
+hipError_t launch_checksum(const uint64_t *data, uint64_t n, uint64_t *acc, hipStream_t s)
+{
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    if (blocks == 0)
+        blocks = 1;
+    checksum_kernel<<<dim3((uint32_t)blocks), dim3(256), 0, s>>>(
+        data, n, reinterpret_cast<unsigned long long *>(acc));
+    return hipGetLastError();
+}
+
+bool batch_cfg_valid(const rngx_batch_cfg &c)
+{
+    const bool s_ok = c.values_per_lane == 64 || c.values_per_lane == 128 ||
+                      c.values_per_lane == 256 || c.values_per_lane == 512 ||
+                      c.values_per_lane == 1024;
+    return s_ok && c.waves_per_block >= 1 && c.waves_per_block <= MAX_WAVES_PER_BLOCK &&
+           c.blocks <= 65536 && c.use_graph <= 1;
+}
+
+hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const uint64_t *pow2,
+                        const uint64_t *rows_s, hipStream_t s)
+{
+    switch (cfg.values_per_lane) {
+    case 64: return launch_batch_s<64>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block, s);
+    case 128: return launch_batch_s<128>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block, s);
+    case 256: return launch_batch_s<256>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block, s);
+    case 512: return launch_batch_s<512>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block, s);
+    default: return launch_batch_s<1024>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block, s);
+    }
+}
+
+} // namespace rngx

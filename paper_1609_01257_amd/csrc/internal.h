@@ -82,11 +82,77 @@ __host__ __device__ __forceinline__ uint64_t init_state(const SeedMix &m, uint32
     return x != 0u ? x : ((uint64_t)m.zero_fix << 32);
 }
 
+// ---- batched streams (batch.hip, batch.cpp) -------------------------------
+// One request as the batch kernel reads it (64 bytes). Requests of length 0
+// are dropped on the host. The seed is folded in already (SeedMix fields).
+struct BatchReq {
+    uint64_t offset;     // value number of the request's first value
+    uint64_t length;     // values requested (> 0)
+    uint64_t base;       // first output index (packed, request order)
+    uint64_t item_begin; // number of the request's first work item
+    uint64_t first_tile; // first tile (of C = 64 * S values) it touches
+    uint32_t gid;
+    uint32_t mix_low;
+    uint32_t mix_high;
+    uint32_t zero_fix;
+    uint64_t reserved;
+};
+static_assert(sizeof(BatchReq) == 64, "BatchReq layout");
+
+// Launch descriptor, read by the kernel from device memory so a captured
+// graph can be replayed with new contents.
+struct BatchDesc {
+    uint64_t *out;
+    const BatchReq *reqs;
+    uint64_t n_items;
+    uint32_t m;
+    uint32_t reserved0;
+    uint64_t reserved1[4];
+};
+static_assert(sizeof(BatchDesc) == 64, "BatchDesc layout");
+
+// A staging/upload slot for one batch in flight (batch.cpp).
+struct BatchSlot {
+    uint32_t capacity = 0;    // requests the buffers hold (power of two)
+    void *staging = nullptr;  // page-locked: BatchDesc + capacity BatchReq
+    void *devtab = nullptr;   // device copy of the same
+    hipEvent_t done = nullptr; // recorded after the slot's last launch
+    hipGraphExec_t exec = nullptr;
+    rngx_batch_cfg exec_cfg{};
+    hipStream_t cap_stream = nullptr;
+    uint32_t m_staged = 0;
+    uint64_t n_items = 0;
+};
+
+bool batch_cfg_valid(const rngx_batch_cfg &c);
+// Caller holds the batch lock (the API functions in batch.cpp take it).
+int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus);
+rngx_batch_cfg resolved_cfg(const rngx_batch_cfg &c, int n_cus);
+int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out,
+                uint64_t out_cap, uint32_t values_per_lane, uint64_t *total_out);
+int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg, hipStream_t stream);
+void release_slot(BatchSlot &slot);
+void release_batch();
+rngx_batch_cfg current_batch_cfg();
+int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *result);
+hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const uint64_t *pow2,
+                        const uint64_t *rows_s, hipStream_t s);
+// Checksum sum_i data[i] * (2 i + 1) mod 2^64 into *acc (device, pre-zeroed).
+hipError_t launch_checksum(const uint64_t *data, uint64_t n, uint64_t *acc, hipStream_t s);
+
+// jump.cpp: host GF(2) tables (64 matrices T^(2^b), 64 rows each).
+const uint64_t *jump_tables();
+uint64_t jump_host(uint64_t x, uint64_t k);
+void power_rows(uint64_t k, uint64_t *rows_out);
+
 // ---- kernel launchers (kernels.hip) ---------------------------------------
 hipError_t launch_init(uint64_t *state, uint32_t n, const SeedMix &mix, hipStream_t s);
 hipError_t launch_gen(const rngx_launch &cfg, bool u32, uint64_t *state, uint32_t n,
                       uint32_t iters, void *out, hipStream_t s);
 bool launch_cfg_valid(const rngx_launch &cfg);
+// copy.hip: device buffer -> page-locked host memory (device-mapped address).
+hipError_t launch_d2h(const void *src, void *dst_mapped, size_t bytes, uint32_t blocks,
+                      hipStream_t s);
 
 // ---- the process-wide generator context (api.cpp) --------------------------
 struct Generator {
@@ -105,6 +171,8 @@ struct Generator {
     hipStream_t pipe_gen = nullptr, pipe_copy = nullptr;
     hipEvent_t gen_done[2] = {nullptr, nullptr};
     hipEvent_t copy_done[2] = {nullptr, nullptr};
+    int copy_mode = RNGX_COPY_KERNEL;
+    uint32_t copy_blocks = 128; // 32+ already saturate PCIe 5.0 x16 on MI355X
 };
 
 Generator &generator();

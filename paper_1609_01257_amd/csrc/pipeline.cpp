@@ -73,6 +73,31 @@ struct SlotEvents {
 
 using namespace rngx;
 
+extern "C" int rngx_set_copy_mode(int mode, uint32_t blocks)
+{
+    Generator &g = generator();
+    std::lock_guard<std::recursive_mutex> lk(g.mu);
+    clear_error();
+    if ((mode != RNGX_COPY_KERNEL && mode != RNGX_COPY_RUNTIME) || blocks == 0 || blocks > 65536)
+        return set_error(RNGX_E_INVAL, "rngx_set_copy_mode: mode must be RNGX_COPY_KERNEL or "
+                                       "RNGX_COPY_RUNTIME and blocks 1..65536");
+    g.copy_mode = mode;
+    g.copy_blocks = blocks;
+    return RNGX_OK;
+}
+
+extern "C" int rngx_get_copy_mode(int *mode, uint32_t *blocks)
+{
+    Generator &g = generator();
+    std::lock_guard<std::recursive_mutex> lk(g.mu);
+    clear_error();
+    if (mode)
+        *mode = g.copy_mode;
+    if (blocks)
+        *blocks = g.copy_blocks;
+    return RNGX_OK;
+}
+
 extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, int u32,
                                    void *dev0, void *dev1, size_t dev_bytes, void *host,
                                    uint32_t host_slots, rngx_consume_fn consume, void *user,
@@ -114,6 +139,16 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
     if (gs == cs)
         return set_error(RNGX_E_INVAL, "stream_to_host: generation and copy streams must differ");
 
+    // Device-mapped address of the host buffer, for the copy kernel.
+    char *hmapped = nullptr;
+    if (g.copy_mode == RNGX_COPY_KERNEL) {
+        void *p = nullptr;
+        if (hipHostGetDevicePointer(&p, host, 0) == hipSuccess && p)
+            hmapped = static_cast<char *>(p);
+        else
+            (void)hipGetLastError(); // not page-locked: use the runtime copy
+    }
+
     SlotEvents slots;
     if (consume) {
         slots.ev.resize(host_slots, nullptr);
@@ -153,12 +188,15 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
         RNGX_HIP(hipEventRecord(g.gen_done[b], gs));
         RNGX_HIP(hipStreamWaitEvent(cs, g.gen_done[b], 0));
         const int tok = prof::begin("READ_BUFFER", cs);
-        hipError_t e = hipMemcpyAsync(hbase + (size_t)slot * step_bytes, dev[b], step_bytes,
-                                      hipMemcpyDeviceToHost, cs);
+        hipError_t e = hmapped
+                           ? launch_d2h(dev[b], hmapped + (size_t)slot * step_bytes, step_bytes,
+                                        g.copy_blocks, cs)
+                           : hipMemcpyAsync(hbase + (size_t)slot * step_bytes, dev[b], step_bytes,
+                                            hipMemcpyDeviceToHost, cs);
         prof::end(tok, cs);
         if (e != hipSuccess) {
             (void)hipStreamSynchronize(cs);
-            return hip_fail(e, "hipMemcpyAsync (device to host)");
+            return hip_fail(e, hmapped ? "device-to-host copy kernel" : "hipMemcpyAsync (D2H)");
         }
         RNGX_HIP(hipEventRecord(g.copy_done[b], cs));
         if (consume)

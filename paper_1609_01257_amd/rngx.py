@@ -20,6 +20,8 @@ RNGX_E_HIP = -3
 RNGX_E_NOMEM = -4
 RNGX_E_BUSY = -5
 RNGX_E_ABORTED = -6
+COPY_KERNEL = 0
+COPY_RUNTIME = 1
 
 CONSUME_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                               ctypes.c_size_t)
@@ -33,6 +35,21 @@ class RngxError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s: %s" % (strerror(code), msg))
         self.code = code
+
+
+class BatchCfg(ctypes.Structure):
+    _fields_ = [("values_per_lane", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
+                ("blocks", ctypes.c_uint32), ("use_graph", ctypes.c_uint32)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("cfg", BatchCfg), ("ms", ctypes.c_double)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", BatchCfg), ("best_ms", ctypes.c_double), ("best_gbs", ctypes.c_double),
+                ("n_tried", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("tried", TuneEntry * 64)]
 
 
 class Launch(ctypes.Structure):
@@ -79,6 +96,15 @@ _SIGS = {
     "rngx_get_launch": ([_int, ctypes.POINTER(Launch)], _int),
     "rngx_stream_to_host": ([_u32, _u32, _int, _p, _p, ctypes.c_size_t, _p, _u32, CONSUME_FN,
                              _p, _p, _p], _int),
+    "rngx_set_copy_mode": ([_int, _u32], _int),
+    "rngx_get_copy_mode": ([ctypes.POINTER(_int), ctypes.POINTER(_u32)], _int),
+    "rngx_generate_batch": ([_p, _u32, _p, _u64, _p], _int),
+    "rngx_set_batch_cfg": ([ctypes.POINTER(BatchCfg)], _int),
+    "rngx_get_batch_cfg": ([ctypes.POINTER(BatchCfg)], _int),
+    "rngx_autotune_batch": ([_p, _u32, _p, _u64, _u32, _p, ctypes.POINTER(TuneResult)], _int),
+    "rngx_checksum": ([_p, _u64, _p, ctypes.POINTER(_u64)], _int),
+    "rngx_initial_state": ([_u64, _u32, ctypes.POINTER(_u64)], _int),
+    "rngx_jump_ahead": ([_u64, _u64, ctypes.POINTER(_u64)], _int),
     "rngx_profile_start": ([], _int),
     "rngx_profile_stop": ([], _int),
     "rngx_profile_enable": ([_int], _int),
@@ -204,6 +230,102 @@ def stream_to_host(n_steps: int, iters_per_step: int, dev0, dev1, host, host_slo
     _check(lib().rngx_stream_to_host(n_steps, iters_per_step, int(u32), dev0.data_ptr(),
                                      dev1.data_ptr(), dev_bytes, host.data_ptr(), host_slots,
                                      cb, None, gs, cs))
+
+
+def set_copy_mode(mode: int, blocks: int = 512):
+    _check(lib().rngx_set_copy_mode(mode, blocks))
+
+
+def get_copy_mode():
+    m, b = _int(), _u32()
+    _check(lib().rngx_get_copy_mode(ctypes.byref(m), ctypes.byref(b)))
+    return m.value, b.value
+
+
+# --- batched streams ----------------------------------------------------------
+
+def req_dtype():
+    import numpy as np
+    return np.dtype([("seed", "<u8"), ("offset", "<u8"), ("length", "<u8"),
+                     ("gid", "<u4"), ("reserved", "<u4")])
+
+
+def make_reqs(seeds, gids, offsets, lengths):
+    """Pack a request table (the rngx_req layout) from four sequences."""
+    import numpy as np
+    r = np.zeros(len(lengths), dtype=req_dtype())
+    r["seed"] = np.asarray(seeds, dtype=np.uint64)
+    r["gid"] = np.asarray(gids, dtype=np.uint32)
+    r["offset"] = np.asarray(offsets, dtype=np.uint64)
+    r["length"] = np.asarray(lengths, dtype=np.uint64)
+    return r
+
+
+def _reqs_arg(reqs):
+    import numpy as np
+    reqs = np.ascontiguousarray(reqs, dtype=req_dtype())
+    return reqs, (reqs.ctypes.data if len(reqs) else None)
+
+
+def generate_batch(reqs, out, stream=None):
+    """out[base_j + t] = V(seed_j, gid_j, offset_j + t), packed in request order."""
+    reqs, ptr = _reqs_arg(reqs)
+    total = int(reqs["length"].sum()) if len(reqs) else 0
+    optr = _device_buffer(out, 8, total) if total else (out.data_ptr() if out is not None else 0)
+    cap = out.numel() if out is not None else 0
+    _check(lib().rngx_generate_batch(ptr, len(reqs), optr, cap, stream_handle(stream)))
+    return total
+
+
+def set_batch_cfg(values_per_lane=256, waves_per_block=4, blocks=0, use_graph=True):
+    cfg = BatchCfg(values_per_lane, waves_per_block, blocks, int(bool(use_graph)))
+    _check(lib().rngx_set_batch_cfg(ctypes.byref(cfg)))
+
+
+def get_batch_cfg():
+    c = BatchCfg()
+    _check(lib().rngx_get_batch_cfg(ctypes.byref(c)))
+    return {"values_per_lane": c.values_per_lane, "waves_per_block": c.waves_per_block,
+            "blocks": c.blocks, "use_graph": bool(c.use_graph)}
+
+
+def _cfg_dict(c):
+    return {"values_per_lane": c.values_per_lane, "waves_per_block": c.waves_per_block,
+            "blocks": c.blocks, "use_graph": bool(c.use_graph)}
+
+
+def autotune_batch(reqs, out, reps=2, stream=None):
+    """Time every batch launch configuration on this table; keep the fastest."""
+    reqs, ptr = _reqs_arg(reqs)
+    total = int(reqs["length"].sum())
+    optr = _device_buffer(out, 8, total)
+    res = TuneResult()
+    _check(lib().rngx_autotune_batch(ptr, len(reqs), optr, out.numel(), reps,
+                                     stream_handle(stream), ctypes.byref(res)))
+    n = min(res.n_tried, 64)
+    return {"best": _cfg_dict(res.best), "best_ms": res.best_ms, "best_gbs": res.best_gbs,
+            "tried": [(_cfg_dict(res.tried[i].cfg), res.tried[i].ms) for i in range(n)]}
+
+
+def checksum(t, n=None, stream=None) -> int:
+    """sum_i t[i] * (2 i + 1) mod 2^64 over the first n uint64 values, on the device."""
+    n = t.numel() if n is None else n
+    ptr = _device_buffer(t, 8, n) if n else t.data_ptr()
+    r = _u64()
+    _check(lib().rngx_checksum(ptr, n, stream_handle(stream), ctypes.byref(r)))
+    return r.value
+
+
+def initial_state(seed: int, gid: int) -> int:
+    r = _u64()
+    _check(lib().rngx_initial_state(seed & (2**64 - 1), gid, ctypes.byref(r)))
+    return r.value
+
+
+def jump_ahead(state: int, k: int) -> int:
+    r = _u64()
+    _check(lib().rngx_jump_ahead(state, k, ctypes.byref(r)))
+    return r.value
 
 
 def shutdown():

@@ -102,3 +102,55 @@ def test_profile_analyze_random_matches_oracle(seed):
 def test_profile_analyze_rejects_backwards_event():
     with pytest.raises(rngx.RngxError):
         rngx.profile_analyze([("K", 0, 10, 5)], 1.0)
+
+
+# --- host-side jump-ahead and seeding (no GPU) ---------------------------------
+
+def test_initial_state_matches_oracle(oracle):
+    rng = np.random.default_rng(9)
+    for seed in [0, 1, 42, 2**64 - 1] + [int(v) for v in rng.integers(0, 2**64, 20, dtype=np.uint64)]:
+        for gid in [0, 1, 2**32 - 1] + [int(v) for v in rng.integers(0, 2**32, 20)]:
+            assert rngx.initial_state(seed, gid) == oracle.init_state(seed, gid)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 63, 64, 65, 1000, 4095, 65536, 123457, 1 << 20])
+def test_jump_ahead_matches_sequential_oracle(oracle, k):
+    for seed, gid in [(0, 0), (42, 7), (2**63, 12345)]:
+        x0 = oracle.init_state(seed, gid)
+        assert rngx.jump_ahead(x0, k) == oracle.value(seed, gid, k)
+
+
+def test_jump_ahead_group_laws(oracle):
+    # T^(2^64 - 1) = I (full period), T^a T^b = T^(a+b), including huge jumps.
+    rng = np.random.default_rng(4)
+    for _ in range(50):
+        x = int(rng.integers(1, 2**64, dtype=np.uint64))
+        assert rngx.jump_ahead(x, 2**64 - 1) == x
+        a = int(rng.integers(0, 2**62, dtype=np.uint64))
+        b = int(rng.integers(0, 2**62, dtype=np.uint64))
+        assert rngx.jump_ahead(rngx.jump_ahead(x, a), b) == rngx.jump_ahead(x, a + b)
+        # One step past a jump equals a jump one further.
+        assert oracle.rng_step(rngx.jump_ahead(x, a)) == rngx.jump_ahead(x, a + 1)
+    assert rngx.jump_ahead(0, 12345) == 0
+
+
+def test_batch_argument_errors_without_gpu():
+    L = rngx.lib()
+    reqs = rngx.make_reqs([1], [0], [0], [4])
+    # NULL request table with m > 0 is rejected before any device work.
+    assert L.rngx_generate_batch(None, 3, None, 0, None) == rngx.RNGX_E_INVAL
+    bad = reqs.copy()
+    bad["reserved"] = 1
+    assert L.rngx_generate_batch(bad.ctypes.data, 1, None, 4, None) == rngx.RNGX_E_INVAL
+    assert "reserved" in rngx.last_error()
+    # Total above the capacity, and a NULL output, are rejected up front.
+    assert L.rngx_generate_batch(reqs.ctypes.data, 1, None, 3, None) == rngx.RNGX_E_INVAL
+    assert L.rngx_generate_batch(reqs.ctypes.data, 1, None, 4, None) == rngx.RNGX_E_INVAL
+    assert L.rngx_generate_batch(reqs.ctypes.data, 1, 8, 4, None) == rngx.RNGX_E_INVAL  # misaligned
+    assert L.rngx_set_batch_cfg(ctypes.byref(rngx.BatchCfg(100, 4, 0, 1))) == rngx.RNGX_E_INVAL
+    assert L.rngx_set_batch_cfg(ctypes.byref(rngx.BatchCfg(256, 5, 0, 1))) == rngx.RNGX_E_INVAL
+    assert L.rngx_set_batch_cfg(ctypes.byref(rngx.BatchCfg(256, 4, 70000, 1))) == rngx.RNGX_E_INVAL
+    rngx.set_batch_cfg(512, 2, 100, False)
+    assert rngx.get_batch_cfg() == {"values_per_lane": 512, "waves_per_block": 2, "blocks": 100,
+                                    "use_graph": False}
+    rngx.set_batch_cfg()

@@ -9,6 +9,15 @@ from paper_1609_01257_amd import inputs, rngx
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(params=["kernel", "runtime"])
+def copy_mode(request):
+    mode = rngx.COPY_KERNEL if request.param == "kernel" else rngx.COPY_RUNTIME
+    old = rngx.get_copy_mode()
+    rngx.set_copy_mode(mode, 512)
+    yield request.param
+    rngx.set_copy_mode(*old)
+
+
 def _buffers(n, R, slots, u32=False):
     dt = torch.int32 if u32 else torch.int64
     dev0 = torch.empty(R * n, dtype=dt, device="cuda")
@@ -19,7 +28,7 @@ def _buffers(n, R, slots, u32=False):
 
 @pytest.mark.parametrize("u32", [False, True])
 @pytest.mark.parametrize("n,R,steps", [(1, 1, 5), (4099, 1, 9), (65537, 3, 4), (1 << 16, 2, 7)])
-def test_every_step_to_its_own_slot(oracle, n, R, steps, u32):
+def test_every_step_to_its_own_slot(oracle, n, R, steps, u32, copy_mode):
     seed = 0 if n == 4099 else 17
     rngx.init(seed, n)
     dev0, dev1, host = _buffers(n, R, steps, u32)
@@ -30,7 +39,7 @@ def test_every_step_to_its_own_slot(oracle, n, R, steps, u32):
     assert rngx.info()[2] == steps * R
 
 
-def test_consumer_sees_steps_in_order_with_two_slots(oracle):
+def test_consumer_sees_steps_in_order_with_two_slots(oracle, copy_mode):
     seed, n, R, steps = 42, 10007, 2, 11
     rngx.init(seed, n)
     dev0, dev1, host = _buffers(n, R, 2)
@@ -80,6 +89,28 @@ def test_consumer_abort_stops_and_reports(oracle):
     assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle.generate(seed, n, 1, cursor=c)[0])
 
 
+def test_pageable_host_memory_uses_runtime_copy(oracle):
+    # Ordinary (not page-locked) host memory cannot be written by the copy
+    # kernel; the pipeline must still deliver every value.
+    seed, n, steps = 12, 5003, 6
+    rngx.init(seed, n)
+    dev0 = torch.empty(n, dtype=torch.int64, device="cuda")
+    dev1 = torch.empty(n, dtype=torch.int64, device="cuda")
+    host = torch.zeros(steps * n, dtype=torch.int64)
+    rngx.stream_to_host(steps, 1, dev0, dev1, host, steps)
+    assert np.array_equal(host.numpy().view(np.uint64).reshape(steps, n),
+                          oracle.generate(seed, n, steps))
+
+
+def test_copy_mode_validation():
+    old = rngx.get_copy_mode()
+    L = rngx.lib()
+    assert L.rngx_set_copy_mode(7, 512) == rngx.RNGX_E_INVAL
+    assert L.rngx_set_copy_mode(0, 0) == rngx.RNGX_E_INVAL
+    assert L.rngx_set_copy_mode(0, 65537) == rngx.RNGX_E_INVAL
+    assert rngx.get_copy_mode() == old
+
+
 def test_stream_argument_errors():
     rngx.init(0, 1024)
     dev0, dev1, host = _buffers(1024, 1, 2)
@@ -119,14 +150,14 @@ def test_profile_of_a_stream_has_fig3_rows():
     ev = rngx.profile_events()
     queues = {name: {q for nm, q, _, _ in ev if nm == name} for name in counts}
     assert len(queues["READ_BUFFER"]) == 1 and queues["READ_BUFFER"] != queues["RNG_KERNEL"]
-    # Copies of one stream are in order and never overlap each other.
+    # Copies on one stream are in order and never overlap each other.
     reads = sorted((s, e) for nm, _, s, e in ev if nm == "READ_BUFFER")
     assert all(reads[i][1] <= reads[i + 1][0] for i in range(len(reads) - 1))
     text = rngx.profile()
     assert "READ_BUFFER" in text and "Time spent in device" in text
 
 
-def test_paper_shaped_streaming_sampled(oracle):
+def test_paper_shaped_streaming_sampled(oracle, copy_mode):
     """4,194,304 work-items, seed 42, 2,000 iterations (32 MiB each) through
     two device buffers and two pinned host slots; every step is checked at
     sampled positions against the oracle, one value at a time."""
