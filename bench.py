@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -199,6 +201,48 @@ def batched(torch, rngx, steps):
     return res
 
 
+def serving(torch, rngx, seconds, plain_gbs):
+    """Serving: 2^20 resident streams, a 16 GB pool with memory-based
+    admission, Poisson arrivals at 2k / 10k / 50k req/s (stream id uniform,
+    length log-uniform in [2^12, 2^22)), results released on completion;
+    then a saturation run (a pre-filled backlog) for throughput."""
+    from paper_1609_01257_amd import inputs
+    pool = torch.empty(16 * 10**9, dtype=torch.uint8, device="cuda")
+    rngx.serve_start(1609, 1 << 20, pool, 4, 1024)
+    res = {"workload": "2^20 resident streams, 16 GB pool, lengths floor(2^U[12,22)), "
+                       "Poisson arrivals, %.0f s per rate" % seconds, "rates": []}
+    try:
+        for rate in (2000.0, 10000.0, 50000.0):
+            t, g, L = inputs.serving_arrivals(rate, seconds)
+            st = rngx.serve_run_trace(t, g, L, timeout_s=seconds + 120)
+            row = {"rate_req_s": rate, "requests": st["completed"],
+                   "offered_gbs": round(8 * float(L.sum()) / seconds / 1e9, 2),
+                   "gbs": round(st["gbs"], 2),
+                   "p50_us": round(st["lat_p50_us"], 1), "p99_us": round(st["lat_p99_us"], 1),
+                   "max_us": round(st["lat_max_us"], 1),
+                   "wait_p99_us": round(st["wait_p99_us"], 1),
+                   "mean_batch": round(st["mean_batch_requests"], 2),
+                   "admission_stalls": st["admission_stalls"]}
+            res["rates"].append(row)
+            log("serving:", row)
+        # Saturation: a backlog of requests all arriving at once.
+        _, g, L = inputs.serving_arrivals(50000.0, 1.0, seed=4242)
+        t = np.zeros(len(g))
+        st = rngx.serve_run_trace(t, g, L, timeout_s=600)
+        res["saturation"] = {"requests": st["completed"], "gb": round(st["bytes"] / 1e9, 2),
+                             "gbs": round(st["gbs"], 1),
+                             "mean_batch": round(st["mean_batch_requests"], 1),
+                             "admission_stalls": st["admission_stalls"],
+                             "p99_us": round(st["lat_p99_us"], 1)}
+        res["saturation"]["served_vs_plain"] = round(st["gbs"] / plain_gbs, 4)
+        log("serving saturation:", res["saturation"])
+    finally:
+        rngx.serve_stop()
+        del pool
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(n_total, iters):
     """The CPU oracle, single-threaded, on the first 2^20 work-items of the
     workload (all iterations)."""
@@ -221,6 +265,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-sweep", action="store_true", help="skip the size/dtype sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="duration of each Poisson serving run (60 for the full runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline kernel (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -287,6 +333,9 @@ def main():
         log("batched ragged streams")
         result["batched"] = batched(torch, rngx, max(3, args.steps // 4))
         log("batched:", result["batched"])
+        log("serving")
+        result["serving"] = serving(torch, rngx, args.serve_seconds,
+                                    result["batched"]["plain_equal_bytes"]["kernel_gbs"])
         log("streaming (two-stream device-to-host pipeline)")
         result["streaming"] = streaming(torch, rngx)
         log("streaming:", result["streaming"])

@@ -256,6 +256,93 @@ int rngx_initial_state(uint64_t seed, uint32_t gid, uint64_t *out);
 int rngx_jump_ahead(uint64_t state, uint64_t k, uint64_t *out);
 
 /* ------------------------------------------------------------------------ */
+/* Serving                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Start the request server. It seeds n_states resident base states
+ * H(seed, g) once (the init kernel) and keeps them on the device; each
+ * stream g then has a cursor that starts at 0. Requests are admitted, in
+ * submission order, as the output pool has room, grouped into launches of
+ * the batched kernel (at most max_batch requests each), and run on up to
+ * n_streams HIP streams at once: requests arriving while others run are
+ * admitted and launched as soon as memory and a stream are free.
+ * pool: caller-owned device memory of pool_bytes bytes, 256-byte aligned,
+ *       kept alive until rngx_serve_stop; results are written into it.
+ * Uses the current batch configuration (values_per_lane, waves_per_block),
+ * launched directly with a grid fitted to each batch.
+ * Errors: RNGX_E_BUSY if already running; RNGX_E_INVAL (n_states == 0, NULL
+ * or misaligned pool, pool_bytes < 256, n_streams outside 1..16,
+ * max_batch == 0); RNGX_E_NOMEM; RNGX_E_HIP. */
+int rngx_serve_start(uint64_t seed, uint32_t n_states, void *pool, uint64_t pool_bytes,
+                     uint32_t n_streams, uint32_t max_batch);
+
+/* Free a request's pool memory as soon as it completes (results unread). */
+#define RNGX_SERVE_AUTORELEASE 1u
+
+/* Submit a request for the next `length` values of stream `stream_id`. The
+ * values are reserved now: if c is the stream's cursor, the result is
+ *     V(seed, stream_id, c + t),  t < length,
+ * and the cursor becomes c + length. The result therefore does not depend on
+ * what the request is batched with or when it runs. *ticket identifies it.
+ * rngx_serve_submit waits while the pending bound (rngx_serve_set_max_pending)
+ * is reached; rngx_serve_try_submit returns RNGX_E_BUSY instead.
+ * Errors: RNGX_E_NOINIT (not running); RNGX_E_INVAL (NULL ticket, stream out
+ * of range, length 0 or above the pool, unknown flags); RNGX_E_BUSY. */
+int rngx_serve_submit(uint32_t stream_id, uint64_t length, uint32_t flags, uint64_t *ticket);
+int rngx_serve_try_submit(uint32_t stream_id, uint64_t length, uint32_t flags,
+                          uint64_t *ticket);
+
+/* State of a request: *done = 1 once its values are in the pool; *values is
+ * their device address once the request is admitted (NULL before).
+ * Errors: RNGX_E_NOINIT; RNGX_E_INVAL (unknown or released ticket). */
+int rngx_serve_poll(uint64_t ticket, uint64_t **values, int *done);
+
+/* Block until the request is done (or timeout_s passes: RNGX_E_BUSY). */
+int rngx_serve_wait(uint64_t ticket, double timeout_s, uint64_t **values);
+
+/* Give a done request's pool memory back (the consumer has read it).
+ * Errors: RNGX_E_INVAL (unknown ticket); RNGX_E_BUSY (not done yet). */
+int rngx_serve_release(uint64_t ticket);
+
+/* Latency is measured from submission to the moment the server sees the
+ * request's batch complete; queue wait from submission to admission. GB/s is
+ * completed output bytes over the time from the first submission to the last
+ * completion since the statistics were reset. */
+typedef struct rngx_serve_report {
+    uint64_t submitted, completed, released;
+    uint64_t pending, admitted, inflight_batches;
+    uint64_t batches, bytes;
+    double elapsed_s, gbs;
+    double lat_p50_us, lat_p99_us, lat_max_us, lat_mean_us;
+    double wait_p50_us, wait_p99_us;
+    uint64_t max_pending, admission_stalls;
+    double mean_batch_requests;
+    uint64_t pool_bytes, pool_used_bytes, pool_peak_bytes;
+} rngx_serve_report;
+
+int rngx_serve_stats(rngx_serve_report *out);
+int rngx_serve_reset_stats(void);
+
+/* Open-loop load driver: submit request i (stream_id[i], length[i], with
+ * RNGX_SERVE_AUTORELEASE) at arrival_s[i] seconds after the call starts
+ * (arrival_s non-decreasing), then wait until every request has completed
+ * (at most timeout_s) and report the statistics of this trace (they are
+ * reset at the start). Errors: as rngx_serve_submit; RNGX_E_BUSY on timeout. */
+int rngx_serve_run_trace(const double *arrival_s, const uint32_t *stream_id,
+                         const uint64_t *length, uint64_t k, double timeout_s,
+                         rngx_serve_report *out);
+
+/* Bound on pending (not yet admitted) requests: submit waits and try_submit
+ * returns RNGX_E_BUSY beyond it (default 2^20; kept across restarts).
+ * Errors: RNGX_E_INVAL if max_pending == 0. */
+int rngx_serve_set_max_pending(uint64_t max_pending);
+
+/* Stop the server: requests not yet launched are dropped, launched batches
+ * are waited for, resident states and streams are freed (the pool is the
+ * caller's). Safe to call when not running. */
+int rngx_serve_stop(void);
+
+/* ------------------------------------------------------------------------ */
 /* Event profiling (the profiler module, Section 4.3; summary of Fig. 3)     */
 /* ------------------------------------------------------------------------ */
 

@@ -195,6 +195,7 @@ int rngx_shutdown(void)
     clear_error();
     int rc = release_state_locked(c);
     release_pipeline_locked(c);
+    release_server();
     release_batch();
     prof::release_all();
     if (c.state_ready)

@@ -70,6 +70,9 @@ void free_slot(BatchSlot &s)
 
 int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus)
 {
+    // Own lock: the server thread reaches here without the batch API lock.
+    static std::mutex tables_mu;
+    std::lock_guard<std::mutex> lk(tables_mu);
     BatchGlobals &g = G();
     int dev = -1;
     RNGX_HIP(hipGetDevice(&dev));
@@ -114,38 +117,13 @@ rngx_batch_cfg resolved_cfg(const rngx_batch_cfg &c, int n_cus)
     return r;
 }
 
-int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out,
-                uint64_t out_cap, uint32_t values_per_lane, uint64_t *total_out)
+int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
+                      uint32_t values_per_lane, const uint64_t *states)
 {
-    if (m && !reqs)
-        return set_error(RNGX_E_INVAL, "batch: reqs is NULL");
-    unsigned __int128 total = 0;
-    uint32_t nonzero = 0;
-    for (uint32_t j = 0; j < m; ++j) {
-        if (reqs[j].reserved)
-            return set_error(RNGX_E_INVAL, "batch: request %u has a nonzero reserved field", j);
-        total += reqs[j].length;
-        nonzero += reqs[j].length != 0;
-    }
-    if (total > (unsigned __int128)UINT64_MAX / 8)
-        return set_error(RNGX_E_INVAL, "batch: total length overflows");
-    if ((uint64_t)total > out_cap)
-        return set_error(RNGX_E_INVAL, "batch: requests need %llu values but out holds %llu",
-                         (unsigned long long)total, (unsigned long long)out_cap);
-    if (total && !out)
-        return set_error(RNGX_E_INVAL, "batch: out is NULL");
-    if (total && (reinterpret_cast<uintptr_t>(out) & 15u))
-        return set_error(RNGX_E_INVAL, "batch: out is not 16-byte aligned");
-    if (total == 0) {
-        *total_out = 0;
-        return RNGX_OK;
-    }
-
-    int rc = RNGX_OK;
     // Grow the slot to a power-of-two capacity (>= 64 requests).
-    if (nonzero > slot.capacity || !slot.staging) {
+    if (k > slot.capacity || !slot.staging) {
         uint32_t cap = 64;
-        while (cap < nonzero)
+        while (cap < k)
             cap <<= 1;
         if (slot.done)
             RNGX_HIP(hipEventSynchronize(slot.done));
@@ -161,11 +139,16 @@ int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out
         slot.capacity = 0;
         const size_t bytes = sizeof(BatchDesc) + (size_t)cap * sizeof(BatchReq);
         hipError_t e = hipHostMalloc(&slot.staging, bytes, hipHostMallocDefault);
-        if (e != hipSuccess)
+        if (e != hipSuccess) {
+            slot.staging = nullptr;
             return hip_fail(e, "hipHostMalloc (batch staging)");
+        }
         e = hipMalloc(&slot.devtab, bytes);
-        if (e != hipSuccess)
+        if (e != hipSuccess) {
+            (void)hipHostFree(slot.staging);
+            slot.staging = slot.devtab = nullptr;
             return hip_fail(e, "hipMalloc (batch table)");
+        }
         slot.capacity = cap;
     }
     if (!slot.done)
@@ -176,50 +159,95 @@ int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out
     const uint64_t C = 64ull * values_per_lane;
     BatchDesc *desc = static_cast<BatchDesc *>(slot.staging);
     BatchReq *tab = reinterpret_cast<BatchReq *>(desc + 1);
-    uint64_t base = 0, items = 0;
-    uint32_t k = 0;
+    uint64_t n_items = 0;
+    for (uint32_t j = 0; j < k; ++j) {
+        const StageReq &q = items[j];
+        BatchReq &r = tab[j];
+        r.offset = q.offset;
+        r.length = q.length;
+        r.vbase = q.vbase;
+        r.item_begin = n_items;
+        r.first_tile = q.vbase / C;
+        r.gid = q.gid;
+        r.mix_low = q.mix.mix_low;
+        r.mix_high = q.mix.mix_high;
+        r.zero_fix = q.mix.zero_fix;
+        r.dst = q.dst;
+        n_items += (q.vbase + q.length - 1) / C - r.first_tile + 1;
+    }
+    std::memset(desc, 0, sizeof *desc);
+    desc->reqs = reinterpret_cast<const BatchReq *>(static_cast<char *>(slot.devtab) +
+                                                    sizeof(BatchDesc));
+    desc->states = states;
+    desc->n_items = n_items;
+    desc->m = k;
+    slot.m_staged = k;
+    slot.n_items = n_items;
+    return RNGX_OK;
+}
+
+int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out,
+                uint64_t out_cap, uint32_t values_per_lane, uint64_t *total_out)
+{
+    if (m && !reqs)
+        return set_error(RNGX_E_INVAL, "batch: reqs is NULL");
+    unsigned __int128 total = 0;
+    for (uint32_t j = 0; j < m; ++j) {
+        if (reqs[j].reserved)
+            return set_error(RNGX_E_INVAL, "batch: request %u has a nonzero reserved field", j);
+        total += reqs[j].length;
+    }
+    if (total > (unsigned __int128)UINT64_MAX / 8)
+        return set_error(RNGX_E_INVAL, "batch: total length overflows");
+    if ((uint64_t)total > out_cap)
+        return set_error(RNGX_E_INVAL, "batch: requests need %llu values but out holds %llu",
+                         (unsigned long long)total, (unsigned long long)out_cap);
+    if (total && !out)
+        return set_error(RNGX_E_INVAL, "batch: out is NULL");
+    if (total && (reinterpret_cast<uintptr_t>(out) & 15u))
+        return set_error(RNGX_E_INVAL, "batch: out is not 16-byte aligned");
+    *total_out = (uint64_t)total;
+    if (total == 0)
+        return RNGX_OK;
+    // Packed layout: the virtual index of a value is its output index.
+    std::vector<StageReq> items;
+    items.reserve(m);
+    uint64_t base = 0;
     for (uint32_t j = 0; j < m; ++j) {
         const uint64_t len = reqs[j].length;
         if (len) {
-            BatchReq &r = tab[k++];
-            const SeedMix mix = seed_mix(reqs[j].seed);
-            r.offset = reqs[j].offset;
-            r.length = len;
-            r.base = base;
-            r.item_begin = items;
-            r.first_tile = base / C;
-            r.gid = reqs[j].gid;
-            r.mix_low = mix.mix_low;
-            r.mix_high = mix.mix_high;
-            r.zero_fix = mix.zero_fix;
-            r.reserved = 0;
-            items += (base + len - 1) / C - r.first_tile + 1;
+            StageReq q;
+            q.offset = reqs[j].offset;
+            q.length = len;
+            q.vbase = base;
+            q.dst = out + base;
+            q.gid = reqs[j].gid;
+            q.mix = seed_mix(reqs[j].seed);
+            items.push_back(q);
         }
         base += len;
     }
-    std::memset(desc, 0, sizeof *desc);
-    desc->out = out;
-    desc->reqs = reinterpret_cast<const BatchReq *>(static_cast<char *>(slot.devtab) +
-                                                    sizeof(BatchDesc));
-    desc->n_items = items;
-    desc->m = k;
-    slot.m_staged = k;
-    slot.n_items = items;
-    *total_out = base;
-    return rc;
+    return batch_stage_items(slot, items.data(), (uint32_t)items.size(), values_per_lane,
+                             nullptr);
 }
 
-int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stream)
+int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stream,
+                 bool fit_grid, const char *prof_name)
 {
     const uint64_t *pow2 = nullptr, *rows_all = nullptr;
     int n_cus = 0;
     int rc = batch_tables_locked(&pow2, &rows_all, &n_cus);
     if (rc)
         return rc;
-    const rngx_batch_cfg cfg = resolved_cfg(cfg_in, n_cus);
+    rngx_batch_cfg cfg = resolved_cfg(cfg_in, n_cus);
+    if (fit_grid && !cfg.use_graph) {
+        const uint64_t need = (slot.n_items + cfg.waves_per_block - 1) / cfg.waves_per_block;
+        if (need < cfg.blocks)
+            cfg.blocks = (uint32_t)std::max<uint64_t>(1, need);
+    }
     const uint64_t *rows_s = rows_all + 64 * s_index(cfg.values_per_lane);
     const BatchDesc *ddesc = static_cast<const BatchDesc *>(slot.devtab);
-    const int tok = prof::begin("BATCH_KERNEL", stream);
+    const int tok = prof::begin(prof_name, stream);
     if (cfg.use_graph) {
         const bool same = slot.exec && slot.exec_cfg.values_per_lane == cfg.values_per_lane &&
                           slot.exec_cfg.waves_per_block == cfg.waves_per_block &&

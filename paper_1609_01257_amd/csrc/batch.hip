@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
     const uint64_t n_items = desc->n_items;
     const uint32_t m = desc->m;
     const BatchReq *__restrict__ reqs = desc->reqs;
-    uint64_t *__restrict__ out = desc->out;
+    const uint64_t *__restrict__ states = desc->states;
     const uint64_t row_s = rows_s[lane];
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
 
@@ -90,7 +90,10 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
                 hi = mid;
         }
         const BatchReq r = reqs[lo];
-        const uint64_t B = r.base, E = r.base + r.length;
+        const uint64_t B = r.vbase, E = r.vbase + r.length;
+        // Output address of virtual index P is obase + P (obase = dst - vbase).
+        uint64_t *__restrict__ obase = reinterpret_cast<uint64_t *>(
+            reinterpret_cast<uintptr_t>(r.dst) - B * sizeof(uint64_t));
         const uint64_t T0 = (r.first_tile + (item - r.item_begin)) * C;
         const uint64_t q0 = T0 > B ? T0 : B;
 
@@ -99,7 +102,8 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
         mix.mix_low = r.mix_low;
         mix.mix_high = r.mix_high;
         mix.zero_fix = r.zero_fix;
-        uint64_t cur = wave_jump(pow2, lane, init_state(mix, r.gid), r.offset + (q0 - B));
+        const uint64_t x0 = states ? states[r.gid] : init_state(mix, r.gid);
+        uint64_t cur = wave_jump(pow2, lane, x0, r.offset + (q0 - B));
         uint64_t curpos = q0;
         uint64_t x = 0;
         for (uint32_t l = 0; l < 64; ++l) {
@@ -148,16 +152,16 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
                 const uint64_t P = T0 + (uint64_t)row * S + (uint64_t)rd * ROUND + 2u * ch;
                 const u64x2 v = *reinterpret_cast<const u64x2 *>(&lds[row * LDS_ROW + 2u * ch]);
                 if (full) {
-                    *reinterpret_cast<u64x2 *>(out + P) = v;
+                    *reinterpret_cast<u64x2 *>(obase + P) = v;
                 } else {
                     const bool v0 = P >= B && P < E;
                     const bool v1 = P + 1 >= B && P + 1 < E;
                     if (v0 && v1)
-                        *reinterpret_cast<u64x2 *>(out + P) = v;
+                        *reinterpret_cast<u64x2 *>(obase + P) = v;
                     else if (v0)
-                        out[P] = v.x;
+                        obase[P] = v.x;
                     else if (v1)
-                        out[P + 1] = v.y;
+                        obase[P + 1] = v.y;
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

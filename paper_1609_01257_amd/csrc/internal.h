@@ -85,25 +85,29 @@ __host__ __device__ __forceinline__ uint64_t init_state(const SeedMix &m, uint32
 // ---- batched streams (batch.hip, batch.cpp) -------------------------------
 // One request as the batch kernel reads it (64 bytes). Requests of length 0
 // are dropped on the host. The seed is folded in already (SeedMix fields).
+// Tiles are laid over a virtual index space in which the request occupies
+// [vbase, vbase + length); value t of the request is stored at dst[t].
 struct BatchReq {
     uint64_t offset;     // value number of the request's first value
     uint64_t length;     // values requested (> 0)
-    uint64_t base;       // first output index (packed, request order)
+    uint64_t vbase;      // first virtual index (tiling only)
     uint64_t item_begin; // number of the request's first work item
     uint64_t first_tile; // first tile (of C = 64 * S values) it touches
     uint32_t gid;
     uint32_t mix_low;
     uint32_t mix_high;
     uint32_t zero_fix;
-    uint64_t reserved;
+    uint64_t *dst;       // destination of value 0 (16-byte alignment of
+                         // dst - vbase, i.e. dst aligned as vbase is even)
 };
 static_assert(sizeof(BatchReq) == 64, "BatchReq layout");
 
 // Launch descriptor, read by the kernel from device memory so a captured
-// graph can be replayed with new contents.
+// graph can be replayed with new contents. With `states` set, a request's
+// stream starts from states[gid] (resident states) instead of H(seed, gid).
 struct BatchDesc {
-    uint64_t *out;
     const BatchReq *reqs;
+    const uint64_t *states;
     uint64_t n_items;
     uint32_t m;
     uint32_t reserved0;
@@ -125,14 +129,28 @@ struct BatchSlot {
 };
 
 bool batch_cfg_valid(const rngx_batch_cfg &c);
-// Caller holds the batch lock (the API functions in batch.cpp take it).
+// Device copies of the jump tables for the current device (thread-safe).
 int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus);
 rngx_batch_cfg resolved_cfg(const rngx_batch_cfg &c, int n_cus);
 int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out,
                 uint64_t out_cap, uint32_t values_per_lane, uint64_t *total_out);
-int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg, hipStream_t stream);
+// One request as staged by a host-side producer (the batch API or the server).
+struct StageReq {
+    uint64_t offset;
+    uint64_t length; // > 0
+    uint64_t vbase;
+    uint64_t *dst;
+    uint32_t gid;
+    SeedMix mix;
+};
+int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
+                      uint32_t values_per_lane, const uint64_t *states);
+// fit_grid: shrink the persistent grid to the staged work (direct launches).
+int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg, hipStream_t stream,
+                 bool fit_grid = false, const char *prof_name = "BATCH_KERNEL");
 void release_slot(BatchSlot &slot);
 void release_batch();
+void release_server(); // serve.cpp: stop the server, free its resources
 rngx_batch_cfg current_batch_cfg();
 int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *result);
 hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const uint64_t *pow2,

@@ -1,0 +1,685 @@
+// Serving: a request loop over resident generator states.
+//
+// rngx_serve_start seeds n_states base states once (the init kernel) and
+// keeps them on the device. A request names one stream g and a length L; at
+// submission it reserves the next L values of g (its cursor c advances by
+// L), so its result, V(seed, g, c + t) for t < L, is fixed when it is
+// submitted and does not depend on which requests it is later batched with
+// or when it runs.
+//
+// One scheduler thread moves requests through three stages:
+//   pending  -> admitted: FIFO, as soon as the output pool (a caller-owned
+//               device buffer) has room for L * 8 bytes;
+//   admitted -> in flight: whenever one of the K launch streams is idle,
+//               every admitted request (up to max_batch) goes into one
+//               launch of the batched kernel, whose table the request's
+//               stream start is jumped to from its resident base state;
+//   in flight -> done: the stream's completion event is polled; latency is
+//               measured from submission to the moment completion is seen.
+// So requests arriving while others run are admitted and launched on another
+// stream as soon as memory and a stream free up (continuous batching), and
+// up to K batches overlap on the device. A consumer reads a done request's
+// values in the pool and releases them; requests submitted with
+// RNGX_SERVE_AUTORELEASE free their memory on completion.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+namespace rngx {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+uint64_t now_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               Clock::now().time_since_epoch())
+        .count();
+}
+
+// First-fit allocator over [0, size) in 256-byte granules, with coalescing.
+class PoolAlloc {
+  public:
+    void reset(uint64_t size)
+    {
+        free_.clear();
+        sizes_.clear();
+        if (size)
+            free_[0] = size;
+        used_ = peak_ = 0;
+    }
+    bool alloc(uint64_t bytes, uint64_t *off)
+    {
+        bytes = (bytes + 255) & ~(uint64_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes)
+                continue;
+            *off = it->first;
+            const uint64_t rest = it->second - bytes, start = it->first + bytes;
+            free_.erase(it);
+            if (rest)
+                free_[start] = rest;
+            sizes_[*off] = bytes;
+            used_ += bytes;
+            peak_ = std::max(peak_, used_);
+            return true;
+        }
+        return false;
+    }
+    void release(uint64_t off)
+    {
+        auto s = sizes_.find(off);
+        if (s == sizes_.end())
+            return;
+        uint64_t start = off, size = s->second;
+        sizes_.erase(s);
+        used_ -= size;
+        auto next = free_.lower_bound(start);
+        if (next != free_.end() && start + size == next->first) {
+            size += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == start) {
+                prev->second += size;
+                return;
+            }
+        }
+        free_[start] = size;
+    }
+    uint64_t used() const { return used_; }
+    uint64_t peak() const { return peak_; }
+    void reset_peak() { peak_ = used_; }
+
+  private:
+    std::map<uint64_t, uint64_t> free_;  // offset -> size
+    std::map<uint64_t, uint64_t> sizes_; // allocated offset -> size
+    uint64_t used_ = 0, peak_ = 0;
+};
+
+enum : uint8_t { ST_PENDING, ST_ADMITTED, ST_INFLIGHT, ST_DONE };
+
+struct SReq {
+    uint32_t gid;
+    uint8_t state;
+    bool autorelease;
+    uint64_t offset, length;
+    uint64_t t_arrive, t_admit, t_done;
+    uint64_t pool_off;
+};
+
+struct Flight {
+    BatchSlot slot;
+    hipStream_t stream = nullptr;
+    std::vector<uint64_t> tickets;
+    bool busy = false;
+};
+
+struct Server {
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool active = false, stopping = false;
+    int device = -1;
+    uint64_t seed = 0;
+    uint32_t n_states = 0;
+    uint64_t *d_states = nullptr;
+    char *pool = nullptr;
+    uint64_t pool_bytes = 0;
+    PoolAlloc alloc;
+    std::vector<uint64_t> cursor;
+    uint64_t next_ticket = 1;
+    std::unordered_map<uint64_t, SReq> reqs;
+    std::deque<uint64_t> pending;
+    std::deque<uint64_t> admitted;
+    std::vector<Flight> flights;
+    uint32_t max_batch = 1024;
+    uint64_t max_pending = 1u << 20;
+    rngx_batch_cfg cfg{256, 4, 0, 0};
+    std::thread worker;
+    int worker_rc = RNGX_OK;
+    std::string worker_msg;
+    // statistics
+    std::vector<uint64_t> lat_ns, wait_ns;
+    uint64_t submitted = 0, completed = 0, released = 0, batches = 0, batch_reqs = 0;
+    uint64_t bytes_done = 0, t_first = 0, t_last = 0, max_pending_seen = 0, stalls = 0;
+    bool stalled = false;
+};
+
+Server &SV()
+{
+    static Server *s = new Server;
+    return *s;
+}
+
+void complete_flight(Server &s, Flight &f)
+{
+    const uint64_t t = now_ns();
+    for (uint64_t tk : f.tickets) {
+        auto it = s.reqs.find(tk);
+        if (it == s.reqs.end())
+            continue;
+        SReq &r = it->second;
+        r.t_done = t;
+        s.lat_ns.push_back(t - r.t_arrive);
+        s.bytes_done += r.length * 8;
+        ++s.completed;
+        s.t_last = t;
+        if (r.autorelease) {
+            s.alloc.release(r.pool_off);
+            ++s.released;
+            s.reqs.erase(it);
+        } else {
+            r.state = ST_DONE;
+        }
+    }
+    f.tickets.clear();
+    f.busy = false;
+}
+
+// Admit, FIFO, while the pool has room for the request at the head.
+bool admit(Server &s)
+{
+    bool progress = false;
+    while (!s.pending.empty()) {
+        SReq &r = s.reqs[s.pending.front()];
+        uint64_t off = 0;
+        if (!s.alloc.alloc(r.length * 8, &off)) {
+            if (!s.stalled) {
+                ++s.stalls;
+                s.stalled = true;
+            }
+            break;
+        }
+        s.stalled = false;
+        r.pool_off = off;
+        r.state = ST_ADMITTED;
+        r.t_admit = now_ns();
+        s.wait_ns.push_back(r.t_admit - r.t_arrive);
+        s.admitted.push_back(s.pending.front());
+        s.pending.pop_front();
+        progress = true;
+    }
+    return progress;
+}
+
+int launch_admitted(Server &s, Flight &f, std::vector<StageReq> &items, const SeedMix &mix)
+{
+    items.clear();
+    uint64_t vbase = 0;
+    while (!s.admitted.empty() && items.size() < s.max_batch) {
+        const uint64_t tk = s.admitted.front();
+        s.admitted.pop_front();
+        SReq &r = s.reqs[tk];
+        StageReq q;
+        q.offset = r.offset;
+        q.length = r.length;
+        q.vbase = vbase;
+        q.dst = reinterpret_cast<uint64_t *>(s.pool + r.pool_off);
+        q.gid = r.gid;
+        q.mix = mix;
+        items.push_back(q);
+        // Next request starts on a 16-value (128-byte) boundary of the
+        // virtual index space, so its lines are whole in its own slice.
+        vbase += (r.length + 15) & ~(uint64_t)15;
+        r.state = ST_INFLIGHT;
+        f.tickets.push_back(tk);
+    }
+    int rc = batch_stage_items(f.slot, items.data(), (uint32_t)items.size(),
+                               s.cfg.values_per_lane, s.d_states);
+    if (rc == RNGX_OK)
+        rc = batch_launch(f.slot, s.cfg, f.stream, true, "SERVE_KERNEL");
+    if (rc == RNGX_OK) {
+        f.busy = true;
+        ++s.batches;
+        s.batch_reqs += items.size();
+    }
+    return rc;
+}
+
+void worker_main(Server *sp)
+{
+    Server &s = *sp;
+    (void)hipSetDevice(s.device);
+    std::vector<StageReq> items;
+    std::unique_lock<std::mutex> lk(s.mu);
+    const SeedMix mix = seed_mix(s.seed); // unused by the kernel: states are resident
+    for (;;) {
+        bool progress = false, busy = false;
+        for (Flight &f : s.flights) {
+            if (!f.busy)
+                continue;
+            const hipError_t q = hipEventQuery(f.slot.done);
+            if (q == hipSuccess) {
+                complete_flight(s, f);
+                progress = true;
+            } else if (q != hipErrorNotReady) {
+                s.worker_rc = hip_fail(q, "serve: batch completion");
+                s.worker_msg = rngx_last_error();
+                f.busy = false;
+            } else {
+                busy = true;
+            }
+        }
+        // Once stopping, nothing new is admitted or launched; batches already
+        // in flight still write into the pool, so they are waited for.
+        if (!s.stopping)
+            progress |= admit(s);
+        while (!s.stopping && !s.admitted.empty()) {
+            Flight *idle = nullptr;
+            for (Flight &f : s.flights)
+                if (!f.busy) {
+                    idle = &f;
+                    break;
+                }
+            if (!idle)
+                break;
+            const int rc = launch_admitted(s, *idle, items, mix);
+            if (rc) {
+                s.worker_rc = rc;
+                s.worker_msg = rngx_last_error();
+                break;
+            }
+            busy = progress = true;
+        }
+        if (progress)
+            s.cv_done.notify_all();
+        if (s.stopping && !busy)
+            break;
+        if (!progress) {
+            if (busy)
+                s.cv_work.wait_for(lk, std::chrono::microseconds(10));
+            else
+                s.cv_work.wait(lk);
+        }
+    }
+}
+
+void reset_stats_locked(Server &s)
+{
+    s.lat_ns.clear();
+    s.wait_ns.clear();
+    s.submitted = s.completed = s.released = s.batches = s.batch_reqs = 0;
+    s.bytes_done = s.t_first = s.t_last = s.max_pending_seen = s.stalls = 0;
+    s.stalled = false;
+    s.alloc.reset_peak(); // live allocations stay
+}
+
+double pct(std::vector<uint64_t> &v, double p)
+{
+    if (v.empty())
+        return 0.0;
+    const size_t k = (size_t)std::min<double>((double)v.size() - 1, p / 100.0 * (double)v.size());
+    std::nth_element(v.begin(), v.begin() + k, v.end());
+    return v[k] * 1e-3;
+}
+
+void fill_stats_locked(Server &s, rngx_serve_report *o)
+{
+    std::memset(o, 0, sizeof *o);
+    o->submitted = s.submitted;
+    o->completed = s.completed;
+    o->released = s.released;
+    o->pending = s.pending.size();
+    o->admitted = s.admitted.size();
+    for (const Flight &f : s.flights)
+        o->inflight_batches += f.busy;
+    o->batches = s.batches;
+    o->bytes = s.bytes_done;
+    o->elapsed_s = s.t_last > s.t_first ? (s.t_last - s.t_first) * 1e-9 : 0.0;
+    o->gbs = o->elapsed_s > 0 ? s.bytes_done / o->elapsed_s / 1e9 : 0.0;
+    std::vector<uint64_t> lat = s.lat_ns, wait = s.wait_ns;
+    o->lat_p50_us = pct(lat, 50.0);
+    o->lat_p99_us = pct(lat, 99.0);
+    o->lat_max_us = lat.empty() ? 0.0 : *std::max_element(lat.begin(), lat.end()) * 1e-3;
+    double sum = 0;
+    for (uint64_t v : s.lat_ns)
+        sum += (double)v;
+    o->lat_mean_us = s.lat_ns.empty() ? 0.0 : sum / s.lat_ns.size() * 1e-3;
+    o->wait_p50_us = pct(wait, 50.0);
+    o->wait_p99_us = pct(wait, 99.0);
+    o->max_pending = s.max_pending_seen;
+    o->admission_stalls = s.stalls;
+    o->mean_batch_requests = s.batches ? (double)s.batch_reqs / s.batches : 0.0;
+    o->pool_bytes = s.pool_bytes;
+    o->pool_used_bytes = s.alloc.used();
+    o->pool_peak_bytes = s.alloc.peak();
+}
+
+int submit_impl(uint32_t stream_id, uint64_t length, uint32_t flags, uint64_t *ticket, bool wait)
+{
+    Server &s = SV();
+    std::unique_lock<std::mutex> lk(s.mu);
+    clear_error();
+    if (!s.active || s.stopping)
+        return set_error(RNGX_E_NOINIT, "serve: the server is not running");
+    if (!ticket)
+        return set_error(RNGX_E_INVAL, "serve: ticket is NULL");
+    if (stream_id >= s.n_states)
+        return set_error(RNGX_E_INVAL, "serve: stream %u out of range (%u streams)", stream_id,
+                         s.n_states);
+    if (length == 0 || length > s.pool_bytes / 8)
+        return set_error(RNGX_E_INVAL, "serve: length %llu is 0 or larger than the pool",
+                         (unsigned long long)length);
+    if (flags & ~(uint32_t)RNGX_SERVE_AUTORELEASE)
+        return set_error(RNGX_E_INVAL, "serve: unknown flags 0x%x", flags);
+    if (s.worker_rc)
+        return set_error(s.worker_rc, "serve: scheduler failed: %s", s.worker_msg.c_str());
+    while (s.pending.size() >= s.max_pending) {
+        if (!wait)
+            return set_error(RNGX_E_BUSY, "serve: %llu requests already pending",
+                             (unsigned long long)s.pending.size());
+        s.cv_done.wait(lk);
+        if (!s.active || s.stopping)
+            return set_error(RNGX_E_NOINIT, "serve: the server stopped");
+    }
+    SReq r;
+    r.gid = stream_id;
+    r.state = ST_PENDING;
+    r.autorelease = (flags & RNGX_SERVE_AUTORELEASE) != 0;
+    r.offset = s.cursor[stream_id];
+    r.length = length;
+    r.t_arrive = now_ns();
+    r.t_admit = r.t_done = 0;
+    r.pool_off = 0;
+    s.cursor[stream_id] += length;
+    const uint64_t tk = s.next_ticket++;
+    s.reqs.emplace(tk, r);
+    s.pending.push_back(tk);
+    ++s.submitted;
+    if (!s.t_first)
+        s.t_first = r.t_arrive;
+    s.max_pending_seen = std::max<uint64_t>(s.max_pending_seen, s.pending.size());
+    *ticket = tk;
+    s.cv_work.notify_one();
+    return RNGX_OK;
+}
+
+void stop_locked(Server &s, std::unique_lock<std::mutex> &lk)
+{
+    if (!s.active)
+        return;
+    s.stopping = true;
+    s.cv_work.notify_all();
+    s.cv_done.notify_all();
+    if (s.worker.joinable()) {
+        lk.unlock();
+        s.worker.join();
+        lk.lock();
+    }
+    for (Flight &f : s.flights) {
+        release_slot(f.slot);
+        if (f.stream)
+            (void)hipStreamDestroy(f.stream);
+    }
+    s.flights.clear();
+    if (s.d_states)
+        (void)hipFree(s.d_states);
+    s.d_states = nullptr;
+    s.reqs.clear();
+    s.pending.clear();
+    s.admitted.clear();
+    s.cursor.clear();
+    s.cursor.shrink_to_fit();
+    s.alloc.reset(0);
+    s.active = s.stopping = false;
+}
+
+} // namespace
+
+void release_server()
+{
+    Server &s = SV();
+    std::unique_lock<std::mutex> lk(s.mu);
+    stop_locked(s, lk);
+}
+
+} // namespace rngx
+
+using namespace rngx;
+
+extern "C" int rngx_serve_start(uint64_t seed, uint32_t n_states, void *pool, uint64_t pool_bytes,
+                                uint32_t n_streams, uint32_t max_batch)
+{
+    Server &s = SV();
+    std::unique_lock<std::mutex> lk(s.mu);
+    clear_error();
+    if (s.active)
+        return set_error(RNGX_E_BUSY, "serve: already running; call rngx_serve_stop first");
+    if (n_states == 0 || !pool || pool_bytes < 256 || n_streams == 0 || n_streams > 16 ||
+        max_batch == 0)
+        return set_error(RNGX_E_INVAL, "serve: need n_states >= 1, a pool of >= 256 bytes, "
+                                       "1..16 streams and max_batch >= 1");
+    if (reinterpret_cast<uintptr_t>(pool) & 255u)
+        return set_error(RNGX_E_INVAL, "serve: pool must be 256-byte aligned");
+    int dev = -1;
+    RNGX_HIP(hipGetDevice(&dev));
+    int rc = batch_tables_locked(nullptr, nullptr, nullptr);
+    if (rc)
+        return rc;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, (size_t)n_states * sizeof(uint64_t));
+    if (e != hipSuccess)
+        return hip_fail(e, "serve: hipMalloc (resident states)");
+    s.d_states = static_cast<uint64_t *>(p);
+    s.flights.resize(n_streams);
+    for (Flight &f : s.flights) {
+        e = hipStreamCreateWithFlags(&f.stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "serve: hipStreamCreate");
+            break;
+        }
+    }
+    if (rc == RNGX_OK) {
+        // The resident base states: the init kernel, once.
+        hipStream_t s0 = s.flights[0].stream;
+        const int tok = prof::begin("INIT_KERNEL", s0);
+        e = launch_init(s.d_states, n_states, seed_mix(seed), s0);
+        prof::end(tok, s0);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s0);
+        if (e != hipSuccess)
+            rc = hip_fail(e, "serve: init kernel");
+    }
+    if (rc) {
+        for (Flight &f : s.flights)
+            if (f.stream)
+                (void)hipStreamDestroy(f.stream);
+        s.flights.clear();
+        (void)hipFree(s.d_states);
+        s.d_states = nullptr;
+        return rc;
+    }
+    s.device = dev;
+    s.seed = seed;
+    s.n_states = n_states;
+    s.pool = static_cast<char *>(pool);
+    s.pool_bytes = pool_bytes;
+    s.alloc.reset(pool_bytes & ~(uint64_t)255);
+    s.cursor.assign(n_states, 0);
+    s.max_batch = max_batch;
+    s.cfg = current_batch_cfg();
+    s.cfg.use_graph = 0; // batch sizes vary: launch directly with a fitted grid
+    s.worker_rc = RNGX_OK;
+    s.worker_msg.clear();
+    s.next_ticket = 1;
+    reset_stats_locked(s);
+    s.active = true;
+    s.stopping = false;
+    s.worker = std::thread(worker_main, &s);
+    return RNGX_OK;
+}
+
+extern "C" int rngx_serve_submit(uint32_t stream_id, uint64_t length, uint32_t flags,
+                                 uint64_t *ticket)
+{
+    return submit_impl(stream_id, length, flags, ticket, true);
+}
+
+extern "C" int rngx_serve_try_submit(uint32_t stream_id, uint64_t length, uint32_t flags,
+                                     uint64_t *ticket)
+{
+    return submit_impl(stream_id, length, flags, ticket, false);
+}
+
+extern "C" int rngx_serve_poll(uint64_t ticket, uint64_t **values, int *done)
+{
+    Server &s = SV();
+    std::lock_guard<std::mutex> lk(s.mu);
+    clear_error();
+    if (!s.active)
+        return set_error(RNGX_E_NOINIT, "serve: the server is not running");
+    auto it = s.reqs.find(ticket);
+    if (it == s.reqs.end())
+        return set_error(RNGX_E_INVAL, "serve: unknown or released ticket %llu",
+                         (unsigned long long)ticket);
+    const SReq &r = it->second;
+    if (done)
+        *done = r.state == ST_DONE;
+    if (values)
+        *values = r.state == ST_PENDING ? nullptr
+                                        : reinterpret_cast<uint64_t *>(s.pool + r.pool_off);
+    return RNGX_OK;
+}
+
+extern "C" int rngx_serve_wait(uint64_t ticket, double timeout_s, uint64_t **values)
+{
+    Server &s = SV();
+    std::unique_lock<std::mutex> lk(s.mu);
+    clear_error();
+    const auto deadline = Clock::now() + std::chrono::duration_cast<Clock::duration>(
+                                             std::chrono::duration<double>(timeout_s));
+    for (;;) {
+        if (!s.active)
+            return set_error(RNGX_E_NOINIT, "serve: the server is not running");
+        auto it = s.reqs.find(ticket);
+        if (it == s.reqs.end())
+            return set_error(RNGX_E_INVAL, "serve: unknown or released ticket %llu",
+                             (unsigned long long)ticket);
+        if (it->second.state == ST_DONE) {
+            if (values)
+                *values = reinterpret_cast<uint64_t *>(s.pool + it->second.pool_off);
+            return RNGX_OK;
+        }
+        if (s.worker_rc)
+            return set_error(s.worker_rc, "serve: scheduler failed: %s", s.worker_msg.c_str());
+        if (s.cv_done.wait_until(lk, deadline) == std::cv_status::timeout)
+            return set_error(RNGX_E_BUSY, "serve: ticket %llu not done within %.3f s",
+                             (unsigned long long)ticket, timeout_s);
+    }
+}
+
+extern "C" int rngx_serve_release(uint64_t ticket)
+{
+    Server &s = SV();
+    std::lock_guard<std::mutex> lk(s.mu);
+    clear_error();
+    if (!s.active)
+        return set_error(RNGX_E_NOINIT, "serve: the server is not running");
+    auto it = s.reqs.find(ticket);
+    if (it == s.reqs.end())
+        return set_error(RNGX_E_INVAL, "serve: unknown or released ticket %llu",
+                         (unsigned long long)ticket);
+    if (it->second.state != ST_DONE)
+        return set_error(RNGX_E_BUSY, "serve: ticket %llu is not done yet",
+                         (unsigned long long)ticket);
+    s.alloc.release(it->second.pool_off);
+    ++s.released;
+    s.reqs.erase(it);
+    s.cv_work.notify_one(); // memory freed: admission may proceed
+    return RNGX_OK;
+}
+
+extern "C" int rngx_serve_stats(rngx_serve_report *out)
+{
+    Server &s = SV();
+    std::lock_guard<std::mutex> lk(s.mu);
+    clear_error();
+    if (!out)
+        return set_error(RNGX_E_INVAL, "serve: stats is NULL");
+    if (!s.active)
+        return set_error(RNGX_E_NOINIT, "serve: the server is not running");
+    fill_stats_locked(s, out);
+    return RNGX_OK;
+}
+
+extern "C" int rngx_serve_reset_stats(void)
+{
+    Server &s = SV();
+    std::lock_guard<std::mutex> lk(s.mu);
+    clear_error();
+    if (!s.active)
+        return set_error(RNGX_E_NOINIT, "serve: the server is not running");
+    reset_stats_locked(s);
+    return RNGX_OK;
+}
+
+extern "C" int rngx_serve_run_trace(const double *arrival_s, const uint32_t *stream_id,
+                                    const uint64_t *length, uint64_t k, double timeout_s,
+                                    rngx_serve_report *out)
+{
+    clear_error();
+    if (k && (!arrival_s || !stream_id || !length))
+        return set_error(RNGX_E_INVAL, "serve: NULL trace arrays");
+    {
+        Server &s = SV();
+        std::lock_guard<std::mutex> lk(s.mu);
+        if (!s.active)
+            return set_error(RNGX_E_NOINIT, "serve: the server is not running");
+        reset_stats_locked(s);
+    }
+    const auto t0 = Clock::now();
+    for (uint64_t i = 0; i < k; ++i) {
+        const auto due = t0 + std::chrono::duration_cast<Clock::duration>(
+                                  std::chrono::duration<double>(arrival_s[i]));
+        while (Clock::now() < due) {
+        }
+        uint64_t tk = 0;
+        const int rc = submit_impl(stream_id[i], length[i], RNGX_SERVE_AUTORELEASE, &tk, true);
+        if (rc)
+            return rc;
+    }
+    Server &s = SV();
+    std::unique_lock<std::mutex> lk(s.mu);
+    const auto deadline = Clock::now() + std::chrono::duration_cast<Clock::duration>(
+                                             std::chrono::duration<double>(timeout_s));
+    while (s.completed < s.submitted) {
+        if (s.worker_rc)
+            return set_error(s.worker_rc, "serve: scheduler failed: %s", s.worker_msg.c_str());
+        if (s.cv_done.wait_until(lk, deadline) == std::cv_status::timeout)
+            return set_error(RNGX_E_BUSY, "serve: trace not drained within %.1f s", timeout_s);
+    }
+    if (out)
+        fill_stats_locked(s, out);
+    return RNGX_OK;
+}
+
+extern "C" int rngx_serve_set_max_pending(uint64_t max_pending)
+{
+    Server &s = SV();
+    std::lock_guard<std::mutex> lk(s.mu);
+    clear_error();
+    if (max_pending == 0)
+        return set_error(RNGX_E_INVAL, "serve: max_pending must be >= 1");
+    s.max_pending = max_pending;
+    s.cv_done.notify_all();
+    return RNGX_OK;
+}
+
+extern "C" int rngx_serve_stop(void)
+{
+    Server &s = SV();
+    std::unique_lock<std::mutex> lk(s.mu);
+    clear_error();
+    stop_locked(s, lk);
+    return RNGX_OK;
+}

@@ -52,6 +52,18 @@ class TuneResult(ctypes.Structure):
                 ("tried", TuneEntry * 64)]
 
 
+class ServeReport(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "released", "pending",
+                                                "admitted", "inflight_batches", "batches",
+                                                "bytes")] + \
+               [(k, ctypes.c_double) for k in ("elapsed_s", "gbs", "lat_p50_us", "lat_p99_us",
+                                                "lat_max_us", "lat_mean_us", "wait_p50_us",
+                                                "wait_p99_us")] + \
+               [("max_pending", ctypes.c_uint64), ("admission_stalls", ctypes.c_uint64),
+                ("mean_batch_requests", ctypes.c_double), ("pool_bytes", ctypes.c_uint64),
+                ("pool_used_bytes", ctypes.c_uint64), ("pool_peak_bytes", ctypes.c_uint64)]
+
+
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
                 ("nontemporal", ctypes.c_uint32)]
@@ -105,6 +117,18 @@ _SIGS = {
     "rngx_checksum": ([_p, _u64, _p, ctypes.POINTER(_u64)], _int),
     "rngx_initial_state": ([_u64, _u32, ctypes.POINTER(_u64)], _int),
     "rngx_jump_ahead": ([_u64, _u64, ctypes.POINTER(_u64)], _int),
+    "rngx_serve_start": ([_u64, _u32, _p, _u64, _u32, _u32], _int),
+    "rngx_serve_submit": ([_u32, _u64, _u32, ctypes.POINTER(_u64)], _int),
+    "rngx_serve_try_submit": ([_u32, _u64, _u32, ctypes.POINTER(_u64)], _int),
+    "rngx_serve_poll": ([_u64, ctypes.POINTER(_p), ctypes.POINTER(_int)], _int),
+    "rngx_serve_wait": ([_u64, ctypes.c_double, ctypes.POINTER(_p)], _int),
+    "rngx_serve_release": ([_u64], _int),
+    "rngx_serve_stats": ([ctypes.POINTER(ServeReport)], _int),
+    "rngx_serve_reset_stats": ([], _int),
+    "rngx_serve_run_trace": ([_p, _p, _p, _u64, ctypes.c_double, ctypes.POINTER(ServeReport)],
+                             _int),
+    "rngx_serve_set_max_pending": ([_u64], _int),
+    "rngx_serve_stop": ([], _int),
     "rngx_profile_start": ([], _int),
     "rngx_profile_stop": ([], _int),
     "rngx_profile_enable": ([_int], _int),
@@ -326,6 +350,79 @@ def jump_ahead(state: int, k: int) -> int:
     r = _u64()
     _check(lib().rngx_jump_ahead(state, k, ctypes.byref(r)))
     return r.value
+
+
+# --- serving --------------------------------------------------------------------
+
+SERVE_AUTORELEASE = 1
+
+
+def serve_start(seed: int, n_states: int, pool, n_streams: int = 4, max_batch: int = 1024):
+    """Start the server over a caller-owned device pool (a CUDA tensor)."""
+    if not pool.is_cuda or not pool.is_contiguous():
+        raise TypeError("pool must be a contiguous device tensor")
+    _check(lib().rngx_serve_start(seed & (2**64 - 1), n_states, pool.data_ptr(),
+                                  pool.numel() * pool.element_size(), n_streams, max_batch))
+
+
+def serve_submit(stream_id: int, length: int, autorelease: bool = False, wait: bool = True) -> int:
+    t = _u64()
+    f = lib().rngx_serve_submit if wait else lib().rngx_serve_try_submit
+    _check(f(stream_id, length, SERVE_AUTORELEASE if autorelease else 0, ctypes.byref(t)))
+    return t.value
+
+
+def serve_poll(ticket: int):
+    """(device address of the values or None, done)."""
+    p, d = _p(), _int()
+    _check(lib().rngx_serve_poll(ticket, ctypes.byref(p), ctypes.byref(d)))
+    return p.value, bool(d.value)
+
+
+def serve_wait(ticket: int, timeout_s: float = 30.0) -> int:
+    p = _p()
+    _check(lib().rngx_serve_wait(ticket, timeout_s, ctypes.byref(p)))
+    return p.value
+
+
+def serve_release(ticket: int):
+    _check(lib().rngx_serve_release(ticket))
+
+
+def _report(r: ServeReport) -> dict:
+    return {name: getattr(r, name) for name, _ in ServeReport._fields_}
+
+
+def serve_stats() -> dict:
+    r = ServeReport()
+    _check(lib().rngx_serve_stats(ctypes.byref(r)))
+    return _report(r)
+
+
+def serve_reset_stats():
+    _check(lib().rngx_serve_reset_stats())
+
+
+def serve_run_trace(arrival_s, stream_id, length, timeout_s: float = 600.0) -> dict:
+    """Open-loop load: request i at arrival_s[i] seconds; returns the trace's stats."""
+    import numpy as np
+    a = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    g = np.ascontiguousarray(stream_id, dtype=np.uint32)
+    n = np.ascontiguousarray(length, dtype=np.uint64)
+    if not (len(a) == len(g) == len(n)):
+        raise ValueError("trace arrays differ in length")
+    r = ServeReport()
+    _check(lib().rngx_serve_run_trace(a.ctypes.data, g.ctypes.data, n.ctypes.data, len(a),
+                                      timeout_s, ctypes.byref(r)))
+    return _report(r)
+
+
+def serve_set_max_pending(n: int):
+    _check(lib().rngx_serve_set_max_pending(n))
+
+
+def serve_stop():
+    _check(lib().rngx_serve_stop())
 
 
 def shutdown():

@@ -154,3 +154,17 @@ def test_batch_argument_errors_without_gpu():
     assert rngx.get_batch_cfg() == {"values_per_lane": 512, "waves_per_block": 2, "blocks": 100,
                                     "use_graph": False}
     rngx.set_batch_cfg()
+
+
+def test_serve_calls_before_start_are_noinit():
+    L = rngx.lib()
+    t = rngx._u64()
+    assert L.rngx_serve_submit(0, 1, 0, ctypes.byref(t)) == rngx.RNGX_E_NOINIT
+    assert L.rngx_serve_try_submit(0, 1, 0, ctypes.byref(t)) == rngx.RNGX_E_NOINIT
+    assert L.rngx_serve_release(1) == rngx.RNGX_E_NOINIT
+    assert L.rngx_serve_stats(ctypes.byref(rngx.ServeReport())) == rngx.RNGX_E_NOINIT
+    assert L.rngx_serve_stop() == rngx.RNGX_OK
+    # Start-argument checks happen before any device work.
+    assert L.rngx_serve_start(1, 0, 4096, 1 << 16, 4, 16) == rngx.RNGX_E_INVAL
+    assert L.rngx_serve_start(1, 10, 4096 + 8, 1 << 16, 4, 16) == rngx.RNGX_E_INVAL
+    assert L.rngx_serve_set_max_pending(0) == rngx.RNGX_E_INVAL

@@ -1,0 +1,179 @@
+"""GPU tests of the request server: parity with the oracle's served-cursor
+rule, identical results alone and in a concurrent mix, admission by pool
+memory, and error paths."""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1609_01257_amd import inputs, rngx
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def server():
+    pools = []
+
+    def start(seed, n_states, pool_bytes, n_streams=4, max_batch=1024):
+        pool = torch.zeros(pool_bytes, dtype=torch.uint8, device="cuda")
+        pools.append(pool)
+        rngx.serve_start(seed, n_states, pool, n_streams, max_batch)
+        return pool
+    yield start
+    rngx.serve_stop()
+    rngx.serve_set_max_pending(1 << 20)
+    pools.clear()
+    torch.cuda.empty_cache()
+
+
+def _values(pool, ptr, length):
+    off = ptr - pool.data_ptr()
+    assert 0 <= off and off + 8 * length <= pool.numel()
+    return pool[off:off + 8 * length].view(torch.int64).cpu().numpy().view(np.uint64)
+
+
+def _history(seed, k, n_streams, max_len):
+    rng = np.random.default_rng(seed)
+    g = rng.integers(0, n_streams, k)
+    L = rng.integers(1, max_len + 1, k)
+    return [(int(a), int(b)) for a, b in zip(g, L)]
+
+
+def test_results_follow_the_cursor_rule(oracle, server):
+    seed = 2024
+    pool = server(seed, 1000, 64 << 20)
+    subs = [(5, 3), (7, 2), (5, 4000), (5, 1), (999, 65537), (7, 3), (0, 16), (5, 17)]
+    tickets = [rngx.serve_submit(g, L) for g, L in subs]
+    exp = oracle.serve_expected(seed, subs)
+    for t, (g, L), e in zip(tickets, subs, exp):
+        ptr = rngx.serve_wait(t, 30.0)
+        assert np.array_equal(_values(pool, ptr, L), e), (g, L)
+        rngx.serve_release(t)
+    st = rngx.serve_stats()
+    assert st["completed"] == len(subs) and st["released"] == len(subs)
+    assert st["pool_used_bytes"] == 0
+
+
+def test_alone_and_in_the_mix_are_identical(oracle, server):
+    seed, n_states = 99, 64
+    hist = _history(1, 400, n_states, 100000)
+    # Mix: everything submitted at once, many batches in flight on 4 streams.
+    pool = server(seed, n_states, 1 << 30, 4, 64)
+    tickets = [rngx.serve_submit(g, L) for g, L in hist]
+    mixed = []
+    for t, (g, L) in zip(tickets, hist):
+        mixed.append(_values(pool, rngx.serve_wait(t, 60.0), L).copy())
+        rngx.serve_release(t)
+    st = rngx.serve_stats()
+    assert st["batches"] < len(hist), "requests were never batched together"
+    rngx.serve_stop()
+    # Alone: the same history, one request at a time.
+    pool = server(seed, n_states, 1 << 30, 1, 1)
+    for (g, L), m in zip(hist, mixed):
+        t = rngx.serve_submit(g, L)
+        got = _values(pool, rngx.serve_wait(t, 30.0), L)
+        rngx.serve_release(t)
+        assert np.array_equal(got, m), (g, L)
+    # And both equal the oracle.
+    exp = oracle.serve_expected(seed, hist)
+    for m, e in zip(mixed, exp):
+        assert np.array_equal(m, e)
+
+
+def test_admission_waits_for_pool_memory_in_fifo_order(oracle, server):
+    seed = 5
+    pool = server(seed, 16, 1 << 20)            # room for two 400 KB requests
+    L = 50000
+    t = [rngx.serve_submit(i, L) for i in range(4)]
+    p0 = rngx.serve_wait(t[0], 30.0)
+    rngx.serve_wait(t[1], 30.0)
+    time.sleep(0.05)
+    assert rngx.serve_poll(t[2]) == (None, False)     # still pending: no memory
+    assert rngx.serve_poll(t[3]) == (None, False)
+    with pytest.raises(rngx.RngxError) as ei:
+        rngx.serve_release(t[2])                      # not done yet
+    assert ei.value.code == rngx.RNGX_E_BUSY
+    exp0 = oracle.serve_expected(seed, [(0, L)])[0]
+    assert np.array_equal(_values(pool, p0, L), exp0)
+    rngx.serve_release(t[0])
+    rngx.serve_wait(t[2], 30.0)                       # admitted into the freed space
+    time.sleep(0.05)
+    assert rngx.serve_poll(t[3])[1] is False          # FIFO: 3 waits behind nothing but memory
+    rngx.serve_release(t[1])
+    rngx.serve_wait(t[3], 30.0)
+    st = rngx.serve_stats()
+    assert st["admission_stalls"] >= 1 and st["pool_peak_bytes"] <= 1 << 20
+    for x in t[2:]:
+        rngx.serve_release(x)
+
+
+def test_try_submit_reports_busy(server):
+    server(1, 8, 1 << 16)                             # 65,536 bytes
+    rngx.serve_set_max_pending(2)
+    big = rngx.serve_submit(0, 8000)                  # fills the pool
+    rngx.serve_wait(big, 30.0)
+    a = rngx.serve_submit(1, 8000)                    # pending (no memory)
+    b = rngx.serve_submit(2, 8000)                    # pending
+    with pytest.raises(rngx.RngxError) as ei:
+        rngx.serve_submit(3, 8000, wait=False)
+    assert ei.value.code == rngx.RNGX_E_BUSY
+    rngx.serve_release(big)
+    for x in (a, b):
+        rngx.serve_wait(x, 30.0)
+        rngx.serve_release(x)
+
+
+def test_argument_errors(server):
+    L = rngx.lib()
+    t = rngx._u64()
+    assert L.rngx_serve_submit(0, 1, 0, rngx.ctypes.byref(t)) == rngx.RNGX_E_NOINIT
+    server(1, 10, 1 << 16)
+    assert L.rngx_serve_submit(10, 1, 0, rngx.ctypes.byref(t)) == rngx.RNGX_E_INVAL   # stream
+    assert L.rngx_serve_submit(0, 0, 0, rngx.ctypes.byref(t)) == rngx.RNGX_E_INVAL    # length 0
+    assert L.rngx_serve_submit(0, 8193, 0, rngx.ctypes.byref(t)) == rngx.RNGX_E_INVAL # > pool
+    assert L.rngx_serve_submit(0, 1, 4, rngx.ctypes.byref(t)) == rngx.RNGX_E_INVAL    # flags
+    assert L.rngx_serve_submit(0, 1, 0, None) == rngx.RNGX_E_INVAL
+    assert L.rngx_serve_release(123456) == rngx.RNGX_E_INVAL
+    pool2 = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
+    assert L.rngx_serve_start(1, 10, pool2.data_ptr(), 1 << 16, 4, 16) == rngx.RNGX_E_BUSY
+
+
+def test_start_argument_errors():
+    L = rngx.lib()
+    pool = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
+    for args in [(1, 0, pool.data_ptr(), 1 << 16, 4, 16), (1, 10, None, 1 << 16, 4, 16),
+                 (1, 10, pool.data_ptr(), 100, 4, 16), (1, 10, pool.data_ptr(), 1 << 16, 0, 16),
+                 (1, 10, pool.data_ptr(), 1 << 16, 17, 16), (1, 10, pool.data_ptr(), 1 << 16, 4, 0),
+                 (1, 10, pool.data_ptr() + 8, 1 << 16, 4, 16)]:
+        assert L.rngx_serve_start(*args) == rngx.RNGX_E_INVAL, args
+
+
+def test_poisson_trace_small(server):
+    server(7, 1 << 20, 1 << 30)
+    t, g, L = inputs.serving_arrivals(2000.0, 0.5, lo_log2=12, hi_log2=16)
+    st = rngx.serve_run_trace(t, g, L, timeout_s=60)
+    assert st["submitted"] == len(t) == st["completed"] == st["released"]
+    assert st["bytes"] == 8 * int(L.sum())
+    assert 0 < st["lat_p50_us"] <= st["lat_p99_us"] <= st["lat_max_us"]
+    assert st["gbs"] > 0 and st["pool_used_bytes"] == 0
+
+
+def test_serving_shape_sampled(oracle, server):
+    """2^20 resident streams, a 16 GB pool, lengths log-uniform in
+    [2^12, 2^22): 300 requests (stream ids uniform, so a few repeat and
+    continue their cursor) submitted together, every one checked in full."""
+    seed = 1609
+    pool = server(seed, 1 << 20, 16 * 10**9 // 256 * 256)
+    _, g, L = inputs.serving_arrivals(10000.0, 0.03, seed=77)
+    g, L = g[:300], L[:300]
+    g[::7] = g[0]                       # force cursor continuation on one stream
+    hist = [(int(a), int(b)) for a, b in zip(g, L)]
+    tickets = [rngx.serve_submit(a, b) for a, b in hist]
+    exp = oracle.serve_expected(seed, hist)
+    for tk, (a, b), e in zip(tickets, hist, exp):
+        got = _values(pool, rngx.serve_wait(tk, 60.0), b)
+        rngx.serve_release(tk)
+        assert np.array_equal(got, e), (a, b)
