@@ -221,6 +221,8 @@ def serving(torch, rngx, seconds, plain_gbs):
                    "p50_us": round(st["lat_p50_us"], 1), "p99_us": round(st["lat_p99_us"], 1),
                    "max_us": round(st["lat_max_us"], 1),
                    "wait_p99_us": round(st["wait_p99_us"], 1),
+                   "launch_p50_us": round(st["launch_p50_us"], 1),
+                   "exec_p50_us": round(st["exec_p50_us"], 1),
                    "mean_batch": round(st["mean_batch_requests"], 2),
                    "admission_stalls": st["admission_stalls"]}
             res["rates"].append(row)

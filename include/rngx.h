@@ -208,19 +208,23 @@ int rngx_generate_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_
  *   256, 512 or 1024); a work item is a tile of 64 * S output values.
  * waves_per_block: 1..4; blocks: 1..65536 (the persistent grid);
  * use_graph: 1 to capture the table upload and the launch in a HIP graph
- *   once and replay it, 0 to launch directly.
+ *   once and replay it, 0 to launch directly;
+ * row_values: values each lane stages in LDS per round before the wave
+ *   writes them out (8: 64-byte rows, 5 KiB of LDS per wave; 16: 128-byte
+ *   rows, 9 KiB per wave).
  * The output never depends on the configuration. */
 typedef struct rngx_batch_cfg {
     uint32_t values_per_lane;
     uint32_t waves_per_block;
     uint32_t blocks;
     uint32_t use_graph;
+    uint32_t row_values;
 } rngx_batch_cfg;
 
 int rngx_set_batch_cfg(const rngx_batch_cfg *cfg);
 int rngx_get_batch_cfg(rngx_batch_cfg *cfg);
 
-#define RNGX_TUNE_MAX 64
+#define RNGX_TUNE_MAX 128
 typedef struct rngx_tune_entry {
     rngx_batch_cfg cfg;
     double ms; /* mean kernel time over the timed repetitions */
@@ -236,7 +240,7 @@ typedef struct rngx_tune_result {
 
 /* Autotuner (the paper's work-size suggestion, Section 6.1, made empirical):
  * time every candidate launch configuration (values_per_lane x
- * waves_per_block x grid size) on this request table with HIP events, check
+ * waves_per_block x waves per compute unit x row_values) on this request table with HIP events, check
  * that every candidate's output has the same checksum, keep the fastest as
  * the batch configuration, and report all of them. `out` receives the
  * requests' output. reps: timed launches per candidate (>= 1).
@@ -264,8 +268,9 @@ int rngx_jump_ahead(uint64_t state, uint64_t k, uint64_t *out);
  * stream g then has a cursor that starts at 0. Requests are admitted, in
  * submission order, as the output pool has room, grouped into launches of
  * the batched kernel (at most max_batch requests each), and run on up to
- * n_streams HIP streams at once: requests arriving while others run are
- * admitted and launched as soon as memory and a stream are free.
+ * n_streams HIP streams at once, with up to two launches queued per stream:
+ * requests arriving while others run are admitted and launched as soon as
+ * memory and a launch slot are free.
  * pool: caller-owned device memory of pool_bytes bytes, 256-byte aligned,
  *       kept alive until rngx_serve_stop; results are written into it.
  * Uses the current batch configuration (values_per_lane, waves_per_block),
@@ -292,6 +297,12 @@ int rngx_serve_submit(uint32_t stream_id, uint64_t length, uint32_t flags, uint6
 int rngx_serve_try_submit(uint32_t stream_id, uint64_t length, uint32_t flags,
                           uint64_t *ticket);
 
+/* Submit k requests at once (one lock acquisition), in array order, with the
+ * semantics of rngx_serve_submit; tickets (optional) receives their tickets.
+ * On an error, the requests before the failing one have been submitted. */
+int rngx_serve_submit_many(const uint32_t *stream_ids, const uint64_t *lengths, uint64_t k,
+                           uint32_t flags, uint64_t *tickets);
+
 /* State of a request: *done = 1 once its values are in the pool; *values is
  * their device address once the request is admitted (NULL before).
  * Errors: RNGX_E_NOINIT; RNGX_E_INVAL (unknown or released ticket). */
@@ -314,7 +325,9 @@ typedef struct rngx_serve_report {
     uint64_t batches, bytes;
     double elapsed_s, gbs;
     double lat_p50_us, lat_p99_us, lat_max_us, lat_mean_us;
-    double wait_p50_us, wait_p99_us;
+    double wait_p50_us, wait_p99_us;     /* submission -> admission */
+    double launch_p50_us, launch_p99_us; /* submission -> launch issued */
+    double exec_p50_us, exec_p99_us;     /* launch issued -> completion seen */
     uint64_t max_pending, admission_stalls;
     double mean_batch_requests;
     uint64_t pool_bytes, pool_used_bytes, pool_peak_bytes;
@@ -325,7 +338,9 @@ int rngx_serve_reset_stats(void);
 
 /* Open-loop load driver: submit request i (stream_id[i], length[i], with
  * RNGX_SERVE_AUTORELEASE) at arrival_s[i] seconds after the call starts
- * (arrival_s non-decreasing), then wait until every request has completed
+ * (arrival_s non-decreasing; every request already due is submitted in one
+ * call of rngx_serve_submit_many, so equal arrival times form a backlog),
+ * then wait until every request has completed
  * (at most timeout_s) and report the statistics of this trace (they are
  * reset at the start). Errors: as rngx_serve_submit; RNGX_E_BUSY on timeout. */
 int rngx_serve_run_trace(const double *arrival_s, const uint32_t *stream_id,

@@ -39,7 +39,7 @@ struct BatchGlobals {
     uint64_t *d_rows_s = nullptr; // T^S rows for each allowed S (5 x 64)
     uint64_t *d_acc = nullptr;    // checksum accumulator
     uint64_t *h_acc = nullptr;    // page-locked copy of it
-    rngx_batch_cfg cfg{256, 4, 0, 1};
+    rngx_batch_cfg cfg{256, 4, 0, 1, 16};
     BatchSlot api_slot;
 };
 
@@ -251,7 +251,8 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
     if (cfg.use_graph) {
         const bool same = slot.exec && slot.exec_cfg.values_per_lane == cfg.values_per_lane &&
                           slot.exec_cfg.waves_per_block == cfg.waves_per_block &&
-                          slot.exec_cfg.blocks == cfg.blocks;
+                          slot.exec_cfg.blocks == cfg.blocks &&
+                          slot.exec_cfg.row_values == cfg.row_values;
         if (!same) {
             if (slot.exec) {
                 (void)hipGraphExecDestroy(slot.exec);
@@ -359,7 +360,8 @@ extern "C" int rngx_set_batch_cfg(const rngx_batch_cfg *cfg)
     if (!cfg || !batch_cfg_valid(*cfg))
         return set_error(RNGX_E_INVAL, "rngx_set_batch_cfg: values_per_lane must be 64, 128, "
                                        "256, 512 or 1024, waves_per_block 1..4, blocks "
-                                       "0..65536 (0 = 16 waves per compute unit), use_graph 0/1");
+                                       "0..65536 (0 = 16 waves per compute unit), use_graph 0/1, "
+                                       "row_values 8 or 16");
     g.cfg = *cfg;
     return RNGX_OK;
 }
@@ -419,16 +421,25 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
     uint64_t ref_sum = 0, total = 0;
     bool have_ref = false;
     double best = 1e300;
-    const uint32_t wpbs[3] = {1, 2, 4};
-    const uint32_t waves_per_cu[3] = {4, 8, 16};
-    for (uint32_t si = 0; si < 5; ++si) {
-        for (uint32_t wi = 0; wi < 3; ++wi) {
+    // values_per_lane x waves_per_block x waves per compute unit x row length;
+    // combinations whose LDS would not fit the waves per CU are skipped.
+    const uint32_t svals[4] = {128, 256, 512, 1024};
+    const uint32_t wpbs[2] = {2, 4};
+    const uint32_t waves_per_cu[3] = {8, 16, 32};
+    const uint32_t rows[2] = {8, 16};
+    for (uint32_t si = 0; si < 4; ++si) {
+        for (uint32_t wi = 0; wi < 2; ++wi) {
             for (uint32_t oi = 0; oi < 3; ++oi) {
+              for (uint32_t ri = 0; ri < 2; ++ri) {
+                const uint32_t lds_per_wave = 64 * (rows[ri] + 2) * 8;
+                if (waves_per_cu[oi] * lds_per_wave > 160u * 1024u)
+                    continue;
                 rngx_batch_cfg c;
-                c.values_per_lane = kValuesPerLane[si];
+                c.values_per_lane = svals[si];
                 c.waves_per_block = wpbs[wi];
                 c.blocks = (uint32_t)std::max(1, n_cus * (int)waves_per_cu[oi] / (int)wpbs[wi]);
                 c.use_graph = g.cfg.use_graph;
+                c.row_values = rows[ri];
                 rc = batch_stage(g.api_slot, reqs, m, out, out_cap, c.values_per_lane, &total);
                 if (rc)
                     return rc;
@@ -470,6 +481,7 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
                     best = mean;
                     result->best = c;
                 }
+              }
             }
         }
     }

@@ -8,9 +8,9 @@
 // C = 64 * S values aligned to multiples of C. A work item is one (request,
 // tile) pair whose ranges intersect; items are numbered request by request,
 // so item -> request is a binary search over the requests' first item
-// numbers. A fixed grid of wavefronts walks the items with a static stride
-// (every item costs about the same), and every wave leaves the loop when the
-// items run out.
+// numbers. A fixed grid of wavefronts takes items in order from an atomic
+// counter (items differ in cost: head and tail tiles of a request are
+// partial), and every wave leaves the loop when the items run out.
 //
 // Per item, lane l produces the S values of the tile's l-th sub-range. Its
 // starting state comes from GF(2) jump-ahead done by the whole wave at once:
@@ -34,10 +34,19 @@ namespace rngx {
 namespace {
 
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+// Pointers that come from the request table are generic; these casts tell
+// the compiler they address global memory, so it emits global (not flat)
+// loads and stores: flat operations would also count against the LDS wait
+// counter and make every LDS wait stall on outstanding global stores.
+typedef __attribute__((address_space(1))) u64x2 g_u64x2;
+typedef __attribute__((address_space(1))) uint64_t g_u64;
+typedef __attribute__((address_space(1))) const BatchReq g_req;
+typedef __attribute__((address_space(1))) const uint64_t g_cu64;
 
-constexpr int ROUND = 16;        // values per lane per LDS round (one 128-byte line)
-constexpr int LDS_ROW = 18;      // u64 per LDS row: 16 values + 2 padding (bank spread)
+// Each round a lane emits R values (R = 8 or 16: a 64- or 128-byte row of
+// its own output) into its LDS row of R + 2 words (padding spreads banks).
 constexpr int MAX_WAVES_PER_BLOCK = 4;
+__host__ __device__ constexpr int lds_row(int R) { return R + 2; }
 
 __device__ __forceinline__ uint64_t wave_matvec(uint64_t row, uint64_t x)
 {
@@ -58,12 +67,28 @@ __device__ __forceinline__ uint64_t wave_jump(const uint64_t *__restrict__ pow2,
     return x;
 }
 
-template <int S>
+// Next work item for the wave: lane 0 bumps the counter with a (vector)
+// global atomic and the value is broadcast to the wave.
+__device__ __forceinline__ uint64_t next_item(unsigned long long *counter, uint32_t lane)
+{
+    unsigned long long v = 0;
+    if (lane == 0)
+        v = atomicAdd(counter, 1ull);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int S, int R>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict__ desc,
                                                     const uint64_t *__restrict__ pow2,
                                                     const uint64_t *__restrict__ rows_s)
 {
     constexpr uint64_t C = 64ull * S;
+    constexpr int ROUND = R;
+    constexpr int LDS_ROW = lds_row(R);
+    constexpr uint32_t CPR = R / 2;     // 16-byte chunks per row
+    constexpr uint32_t RPI = 64 / CPR;  // rows per store instruction
     extern __shared__ uint64_t lds_dyn[]; // 64 * LDS_ROW u64 per wave
     const uint32_t lane = threadIdx.x & 63u;
     // Wave index, made provably uniform so item bookkeeping runs on the
@@ -73,13 +98,14 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
 
     const uint64_t n_items = desc->n_items;
     const uint32_t m = desc->m;
-    const BatchReq *__restrict__ reqs = desc->reqs;
-    const uint64_t *__restrict__ states = desc->states;
+    g_req *__restrict__ reqs = (g_req *)desc->reqs;
+    g_cu64 *__restrict__ states = (g_cu64 *)desc->states;
     const uint64_t row_s = rows_s[lane];
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    unsigned long long *counter =
+        reinterpret_cast<unsigned long long *>(const_cast<uint64_t *>(&desc->next_item));
 
-    for (uint64_t item = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wid; item < n_items;
-         item += waves) {
+    for (uint64_t item = next_item(counter, lane); item < n_items;
+         item = next_item(counter, lane)) {
         // Request of this item: the last j with item_begin <= item.
         uint32_t lo = 0, hi = m;
         while (hi - lo > 1) {
@@ -89,12 +115,14 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
             else
                 hi = mid;
         }
-        const BatchReq r = reqs[lo];
+        g_req &r = reqs[lo];
         const uint64_t B = r.vbase, E = r.vbase + r.length;
         // Output address of virtual index P is obase + P (obase = dst - vbase).
-        uint64_t *__restrict__ obase = reinterpret_cast<uint64_t *>(
-            reinterpret_cast<uintptr_t>(r.dst) - B * sizeof(uint64_t));
+        g_u64 *__restrict__ obase =
+            (g_u64 *)(reinterpret_cast<uintptr_t>(r.dst) - B * sizeof(uint64_t));
         const uint64_t T0 = (r.first_tile + (item - r.item_begin)) * C;
+        const uint64_t offset = r.offset;
+        const uint32_t gid = r.gid;
         const uint64_t q0 = T0 > B ? T0 : B;
 
         // State at q0, then each active lane's first position.
@@ -102,8 +130,8 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
         mix.mix_low = r.mix_low;
         mix.mix_high = r.mix_high;
         mix.zero_fix = r.zero_fix;
-        const uint64_t x0 = states ? states[r.gid] : init_state(mix, r.gid);
-        uint64_t cur = wave_jump(pow2, lane, x0, r.offset + (q0 - B));
+        const uint64_t x0 = states ? states[gid] : init_state(mix, gid);
+        uint64_t cur = wave_jump(pow2, lane, x0, offset + (q0 - B));
         uint64_t curpos = q0;
         uint64_t x = 0;
         for (uint32_t l = 0; l < 64; ++l) {
@@ -145,19 +173,32 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // Lane l of store instruction i writes 16 bytes of row RPI*i + l/CPR:
+            // CPR lanes cover one row, i.e. one whole 64- or 128-byte segment.
+            const uint32_t ch = lane % CPR;
+            if (full) {
+                u64x2 v[CPR];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const uint32_t row = 8u * i + (lane >> 3);
-                const uint32_t ch = lane & 7u;
-                const uint64_t P = T0 + (uint64_t)row * S + (uint64_t)rd * ROUND + 2u * ch;
-                const u64x2 v = *reinterpret_cast<const u64x2 *>(&lds[row * LDS_ROW + 2u * ch]);
-                if (full) {
-                    *reinterpret_cast<u64x2 *>(obase + P) = v;
-                } else {
+                for (uint32_t i = 0; i < CPR; ++i) {
+                    const uint32_t row = RPI * i + lane / CPR;
+                    v[i] = *reinterpret_cast<const u64x2 *>(&lds[row * LDS_ROW + 2u * ch]);
+                }
+#pragma unroll
+                for (uint32_t i = 0; i < CPR; ++i) {
+                    const uint32_t row = RPI * i + lane / CPR;
+                    const uint64_t P = T0 + (uint64_t)row * S + (uint64_t)rd * ROUND + 2u * ch;
+                    *(g_u64x2 *)(obase + P) = v[i];
+                }
+            } else {
+#pragma unroll
+                for (uint32_t i = 0; i < CPR; ++i) {
+                    const uint32_t row = RPI * i + lane / CPR;
+                    const uint64_t P = T0 + (uint64_t)row * S + (uint64_t)rd * ROUND + 2u * ch;
+                    const u64x2 v = *reinterpret_cast<const u64x2 *>(&lds[row * LDS_ROW + 2u * ch]);
                     const bool v0 = P >= B && P < E;
                     const bool v1 = P + 1 >= B && P + 1 < E;
                     if (v0 && v1)
-                        *reinterpret_cast<u64x2 *>(obase + P) = v;
+                        *(g_u64x2 *)(obase + P) = v;
                     else if (v0)
                         obase[P] = v.x;
                     else if (v1)
@@ -173,11 +214,17 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
 
 template <int S>
 hipError_t launch_batch_s(const BatchDesc *desc, const uint64_t *pow2, const uint64_t *rows_s,
-                          uint32_t blocks, uint32_t waves_per_block, hipStream_t s)
+                          uint32_t blocks, uint32_t waves_per_block, uint32_t row_values,
+                          hipStream_t s)
 {
-    const size_t lds_bytes = (size_t)waves_per_block * 64 * LDS_ROW * sizeof(uint64_t);
-    batch_kernel<S><<<dim3(blocks), dim3(64 * waves_per_block), lds_bytes, s>>>(desc, pow2,
-                                                                               rows_s);
+    const size_t lds_bytes =
+        (size_t)waves_per_block * 64 * lds_row(row_values) * sizeof(uint64_t);
+    if (row_values == 8)
+        batch_kernel<S, 8><<<dim3(blocks), dim3(64 * waves_per_block), lds_bytes, s>>>(
+            desc, pow2, rows_s);
+    else
+        batch_kernel<S, 16><<<dim3(blocks), dim3(64 * waves_per_block), lds_bytes, s>>>(
+            desc, pow2, rows_s);
     return hipGetLastError();
 }
 
@@ -214,18 +261,28 @@ bool batch_cfg_valid(const rngx_batch_cfg &c)
                       c.values_per_lane == 256 || c.values_per_lane == 512 ||
                       c.values_per_lane == 1024;
     return s_ok && c.waves_per_block >= 1 && c.waves_per_block <= MAX_WAVES_PER_BLOCK &&
-           c.blocks <= 65536 && c.use_graph <= 1;
+           c.blocks <= 65536 && c.use_graph <= 1 && (c.row_values == 8 || c.row_values == 16);
 }
 
 hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const uint64_t *pow2,
                         const uint64_t *rows_s, hipStream_t s)
 {
     switch (cfg.values_per_lane) {
-    case 64: return launch_batch_s<64>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block, s);
-    case 128: return launch_batch_s<128>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block, s);
-    case 256: return launch_batch_s<256>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block, s);
-    case 512: return launch_batch_s<512>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block, s);
-    default: return launch_batch_s<1024>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block, s);
+    case 64:
+        return launch_batch_s<64>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block,
+                                 cfg.row_values, s);
+    case 128:
+        return launch_batch_s<128>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block,
+                                 cfg.row_values, s);
+    case 256:
+        return launch_batch_s<256>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block,
+                                 cfg.row_values, s);
+    case 512:
+        return launch_batch_s<512>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block,
+                                 cfg.row_values, s);
+    default:
+        return launch_batch_s<1024>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block,
+                                    cfg.row_values, s);
     }
 }
 

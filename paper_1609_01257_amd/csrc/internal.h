@@ -105,13 +105,16 @@ static_assert(sizeof(BatchReq) == 64, "BatchReq layout");
 // Launch descriptor, read by the kernel from device memory so a captured
 // graph can be replayed with new contents. With `states` set, a request's
 // stream starts from states[gid] (resident states) instead of H(seed, gid).
+// `next_item` is the work counter the waves take items from; it is 0 in the
+// staged copy, so every upload of the table (also a graph replay) resets it.
 struct BatchDesc {
     const BatchReq *reqs;
     const uint64_t *states;
     uint64_t n_items;
     uint32_t m;
     uint32_t reserved0;
-    uint64_t reserved1[4];
+    uint64_t next_item;
+    uint64_t reserved1[3];
 };
 static_assert(sizeof(BatchDesc) == 64, "BatchDesc layout");
 

@@ -21,7 +21,10 @@
 // up to K batches overlap on the device. A consumer reads a done request's
 // values in the pool and releases them; requests submitted with
 // RNGX_SERVE_AUTORELEASE free their memory on completion.
+#include <sys/prctl.h>
+
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -29,10 +32,10 @@
 #include <map>
 #include <mutex>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
+#include "pool.h"
 
 namespace rngx {
 namespace {
@@ -46,67 +49,6 @@ uint64_t now_ns()
         .count();
 }
 
-// First-fit allocator over [0, size) in 256-byte granules, with coalescing.
-class PoolAlloc {
-  public:
-    void reset(uint64_t size)
-    {
-        free_.clear();
-        sizes_.clear();
-        if (size)
-            free_[0] = size;
-        used_ = peak_ = 0;
-    }
-    bool alloc(uint64_t bytes, uint64_t *off)
-    {
-        bytes = (bytes + 255) & ~(uint64_t)255;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes)
-                continue;
-            *off = it->first;
-            const uint64_t rest = it->second - bytes, start = it->first + bytes;
-            free_.erase(it);
-            if (rest)
-                free_[start] = rest;
-            sizes_[*off] = bytes;
-            used_ += bytes;
-            peak_ = std::max(peak_, used_);
-            return true;
-        }
-        return false;
-    }
-    void release(uint64_t off)
-    {
-        auto s = sizes_.find(off);
-        if (s == sizes_.end())
-            return;
-        uint64_t start = off, size = s->second;
-        sizes_.erase(s);
-        used_ -= size;
-        auto next = free_.lower_bound(start);
-        if (next != free_.end() && start + size == next->first) {
-            size += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == start) {
-                prev->second += size;
-                return;
-            }
-        }
-        free_[start] = size;
-    }
-    uint64_t used() const { return used_; }
-    uint64_t peak() const { return peak_; }
-    void reset_peak() { peak_ = used_; }
-
-  private:
-    std::map<uint64_t, uint64_t> free_;  // offset -> size
-    std::map<uint64_t, uint64_t> sizes_; // allocated offset -> size
-    uint64_t used_ = 0, peak_ = 0;
-};
-
 enum : uint8_t { ST_PENDING, ST_ADMITTED, ST_INFLIGHT, ST_DONE };
 
 struct SReq {
@@ -114,13 +56,21 @@ struct SReq {
     uint8_t state;
     bool autorelease;
     uint64_t offset, length;
-    uint64_t t_arrive, t_admit, t_done;
-    uint64_t pool_off;
+    uint64_t t_arrive, t_admit, t_launch, t_done;
+    uint64_t pool_off, pool_seq;
+    bool live;
 };
+
+// A launch slot (staging buffers + completion event). Slots are spread over
+// the launch streams, SLOTS_PER_STREAM each, so every stream can hold a
+// batch queued behind the one it runs: batches that run side by side and
+// finish together do not leave the device idle while the host refills.
+constexpr uint32_t SLOTS_PER_STREAM = 2;
 
 struct Flight {
     BatchSlot slot;
     hipStream_t stream = nullptr;
+    uint32_t stream_index = 0;
     std::vector<uint64_t> tickets;
     bool busy = false;
 };
@@ -135,21 +85,22 @@ struct Server {
     uint64_t *d_states = nullptr;
     char *pool = nullptr;
     uint64_t pool_bytes = 0;
-    PoolAlloc alloc;
+    PoolRing alloc;
     std::vector<uint64_t> cursor;
-    uint64_t next_ticket = 1;
-    std::unordered_map<uint64_t, SReq> reqs;
+    TicketTable<SReq> reqs;
     std::deque<uint64_t> pending;
     std::deque<uint64_t> admitted;
     std::vector<Flight> flights;
+    std::vector<hipStream_t> streams;
     uint32_t max_batch = 1024;
     uint64_t max_pending = 1u << 20;
-    rngx_batch_cfg cfg{256, 4, 0, 0};
+    rngx_batch_cfg cfg{256, 4, 0, 0, 16};
     std::thread worker;
     int worker_rc = RNGX_OK;
     std::string worker_msg;
+    std::atomic<uint64_t> submit_seq{0}; // bumped by every submission (lock-free peek)
     // statistics
-    std::vector<uint64_t> lat_ns, wait_ns;
+    std::vector<uint64_t> lat_ns, wait_ns, launch_ns, exec_ns;
     uint64_t submitted = 0, completed = 0, released = 0, batches = 0, batch_reqs = 0;
     uint64_t bytes_done = 0, t_first = 0, t_last = 0, max_pending_seen = 0, stalls = 0;
     bool stalled = false;
@@ -165,19 +116,21 @@ void complete_flight(Server &s, Flight &f)
 {
     const uint64_t t = now_ns();
     for (uint64_t tk : f.tickets) {
-        auto it = s.reqs.find(tk);
-        if (it == s.reqs.end())
+        SReq *rp = s.reqs.find(tk);
+        if (!rp)
             continue;
-        SReq &r = it->second;
+        SReq &r = *rp;
         r.t_done = t;
         s.lat_ns.push_back(t - r.t_arrive);
+        s.launch_ns.push_back(r.t_launch - r.t_arrive);
+        s.exec_ns.push_back(t - r.t_launch);
         s.bytes_done += r.length * 8;
         ++s.completed;
         s.t_last = t;
         if (r.autorelease) {
-            s.alloc.release(r.pool_off);
+            s.alloc.release(r.pool_seq);
             ++s.released;
-            s.reqs.erase(it);
+            s.reqs.erase(tk);
         } else {
             r.state = ST_DONE;
         }
@@ -191,9 +144,9 @@ bool admit(Server &s)
 {
     bool progress = false;
     while (!s.pending.empty()) {
-        SReq &r = s.reqs[s.pending.front()];
-        uint64_t off = 0;
-        if (!s.alloc.alloc(r.length * 8, &off)) {
+        SReq &r = *s.reqs.find(s.pending.front());
+        uint64_t off = 0, seq = 0;
+        if (!s.alloc.alloc(r.length * 8, &off, &seq)) {
             if (!s.stalled) {
                 ++s.stalls;
                 s.stalled = true;
@@ -202,6 +155,7 @@ bool admit(Server &s)
         }
         s.stalled = false;
         r.pool_off = off;
+        r.pool_seq = seq;
         r.state = ST_ADMITTED;
         r.t_admit = now_ns();
         s.wait_ns.push_back(r.t_admit - r.t_arrive);
@@ -212,6 +166,15 @@ bool admit(Server &s)
     return progress;
 }
 
+// Values per lane for a batch of `values` outputs: short sequential runs
+// (more lanes busy) for small batches, where latency matters, and the
+// configured, tuned length for large ones, where throughput does.
+uint32_t values_per_lane_for(uint64_t values, uint32_t tuned)
+{
+    const uint32_t s = values <= (1u << 20) ? 64u : values <= (1u << 23) ? 256u : tuned;
+    return std::min(s, tuned);
+}
+
 int launch_admitted(Server &s, Flight &f, std::vector<StageReq> &items, const SeedMix &mix)
 {
     items.clear();
@@ -219,7 +182,7 @@ int launch_admitted(Server &s, Flight &f, std::vector<StageReq> &items, const Se
     while (!s.admitted.empty() && items.size() < s.max_batch) {
         const uint64_t tk = s.admitted.front();
         s.admitted.pop_front();
-        SReq &r = s.reqs[tk];
+        SReq &r = *s.reqs.find(tk);
         StageReq q;
         q.offset = r.offset;
         q.length = r.length;
@@ -234,10 +197,15 @@ int launch_admitted(Server &s, Flight &f, std::vector<StageReq> &items, const Se
         r.state = ST_INFLIGHT;
         f.tickets.push_back(tk);
     }
-    int rc = batch_stage_items(f.slot, items.data(), (uint32_t)items.size(),
-                               s.cfg.values_per_lane, s.d_states);
+    rngx_batch_cfg cfg = s.cfg;
+    cfg.values_per_lane = values_per_lane_for(vbase, s.cfg.values_per_lane);
+    int rc = batch_stage_items(f.slot, items.data(), (uint32_t)items.size(), cfg.values_per_lane,
+                               s.d_states);
     if (rc == RNGX_OK)
-        rc = batch_launch(f.slot, s.cfg, f.stream, true, "SERVE_KERNEL");
+        rc = batch_launch(f.slot, cfg, f.stream, true, "SERVE_KERNEL");
+    const uint64_t t = now_ns();
+    for (uint64_t tk : f.tickets)
+        s.reqs.find(tk)->t_launch = t;
     if (rc == RNGX_OK) {
         f.busy = true;
         ++s.batches;
@@ -246,10 +214,21 @@ int launch_admitted(Server &s, Flight &f, std::vector<StageReq> &items, const Se
     return rc;
 }
 
+// Spin for about `ns` nanoseconds without the lock.
+void spin_for(uint64_t ns)
+{
+    const uint64_t until = now_ns() + ns;
+    while (now_ns() < until)
+        __builtin_ia32_pause();
+}
+
 void worker_main(Server *sp)
 {
     Server &s = *sp;
     (void)hipSetDevice(s.device);
+    // Timed waits of this thread should not be stretched by the default
+    // 50 us timer slack.
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0, 0, 0);
     std::vector<StageReq> items;
     std::unique_lock<std::mutex> lk(s.mu);
     const SeedMix mix = seed_mix(s.seed); // unused by the kernel: states are resident
@@ -275,12 +254,20 @@ void worker_main(Server *sp)
         if (!s.stopping)
             progress |= admit(s);
         while (!s.stopping && !s.admitted.empty()) {
+            // An idle slot on the stream with the fewest batches in flight.
             Flight *idle = nullptr;
-            for (Flight &f : s.flights)
-                if (!f.busy) {
+            uint32_t best = ~0u;
+            for (Flight &f : s.flights) {
+                if (f.busy)
+                    continue;
+                uint32_t load = 0;
+                for (const Flight &o : s.flights)
+                    load += o.busy && o.stream_index == f.stream_index;
+                if (load < best) {
+                    best = load;
                     idle = &f;
-                    break;
                 }
+            }
             if (!idle)
                 break;
             const int rc = launch_admitted(s, *idle, items, mix);
@@ -296,10 +283,23 @@ void worker_main(Server *sp)
         if (s.stopping && !busy)
             break;
         if (!progress) {
-            if (busy)
-                s.cv_work.wait_for(lk, std::chrono::microseconds(10));
-            else
-                s.cv_work.wait(lk);
+            if (busy) {
+                // Batches in flight: poll their events again shortly.
+                lk.unlock();
+                spin_for(2000);
+                lk.lock();
+            } else {
+                // Idle: watch for a submission for a while, then sleep.
+                const uint64_t seq = s.submit_seq.load(std::memory_order_acquire);
+                lk.unlock();
+                const uint64_t until = now_ns() + 200000;
+                while (s.submit_seq.load(std::memory_order_acquire) == seq && now_ns() < until)
+                    __builtin_ia32_pause();
+                lk.lock();
+                if (s.submit_seq.load(std::memory_order_acquire) == seq && !s.stopping &&
+                    s.pending.empty() && s.admitted.empty())
+                    s.cv_work.wait_for(lk, std::chrono::milliseconds(5));
+            }
         }
     }
 }
@@ -308,6 +308,8 @@ void reset_stats_locked(Server &s)
 {
     s.lat_ns.clear();
     s.wait_ns.clear();
+    s.launch_ns.clear();
+    s.exec_ns.clear();
     s.submitted = s.completed = s.released = s.batches = s.batch_reqs = 0;
     s.bytes_done = s.t_first = s.t_last = s.max_pending_seen = s.stalls = 0;
     s.stalled = false;
@@ -347,6 +349,11 @@ void fill_stats_locked(Server &s, rngx_serve_report *o)
     o->lat_mean_us = s.lat_ns.empty() ? 0.0 : sum / s.lat_ns.size() * 1e-3;
     o->wait_p50_us = pct(wait, 50.0);
     o->wait_p99_us = pct(wait, 99.0);
+    std::vector<uint64_t> la = s.launch_ns, ex = s.exec_ns;
+    o->launch_p50_us = pct(la, 50.0);
+    o->launch_p99_us = pct(la, 99.0);
+    o->exec_p50_us = pct(ex, 50.0);
+    o->exec_p99_us = pct(ex, 99.0);
     o->max_pending = s.max_pending_seen;
     o->admission_stalls = s.stalls;
     o->mean_batch_requests = s.batches ? (double)s.batch_reqs / s.batches : 0.0;
@@ -355,15 +362,10 @@ void fill_stats_locked(Server &s, rngx_serve_report *o)
     o->pool_peak_bytes = s.alloc.peak();
 }
 
-int submit_impl(uint32_t stream_id, uint64_t length, uint32_t flags, uint64_t *ticket, bool wait)
+int check_request_locked(Server &s, uint32_t stream_id, uint64_t length, uint32_t flags)
 {
-    Server &s = SV();
-    std::unique_lock<std::mutex> lk(s.mu);
-    clear_error();
     if (!s.active || s.stopping)
         return set_error(RNGX_E_NOINIT, "serve: the server is not running");
-    if (!ticket)
-        return set_error(RNGX_E_INVAL, "serve: ticket is NULL");
     if (stream_id >= s.n_states)
         return set_error(RNGX_E_INVAL, "serve: stream %u out of range (%u streams)", stream_id,
                          s.n_states);
@@ -374,6 +376,12 @@ int submit_impl(uint32_t stream_id, uint64_t length, uint32_t flags, uint64_t *t
         return set_error(RNGX_E_INVAL, "serve: unknown flags 0x%x", flags);
     if (s.worker_rc)
         return set_error(s.worker_rc, "serve: scheduler failed: %s", s.worker_msg.c_str());
+    return RNGX_OK;
+}
+
+// Wait (or fail with BUSY) until one more request may be pending.
+int make_room_locked(Server &s, std::unique_lock<std::mutex> &lk, bool wait)
+{
     while (s.pending.size() >= s.max_pending) {
         if (!wait)
             return set_error(RNGX_E_BUSY, "serve: %llu requests already pending",
@@ -382,6 +390,11 @@ int submit_impl(uint32_t stream_id, uint64_t length, uint32_t flags, uint64_t *t
         if (!s.active || s.stopping)
             return set_error(RNGX_E_NOINIT, "serve: the server stopped");
     }
+    return RNGX_OK;
+}
+
+uint64_t enqueue_locked(Server &s, uint32_t stream_id, uint64_t length, uint32_t flags)
+{
     SReq r;
     r.gid = stream_id;
     r.state = ST_PENDING;
@@ -389,17 +402,55 @@ int submit_impl(uint32_t stream_id, uint64_t length, uint32_t flags, uint64_t *t
     r.offset = s.cursor[stream_id];
     r.length = length;
     r.t_arrive = now_ns();
-    r.t_admit = r.t_done = 0;
-    r.pool_off = 0;
+    r.t_admit = r.t_launch = r.t_done = 0;
+    r.pool_off = r.pool_seq = 0;
+    r.live = true;
     s.cursor[stream_id] += length;
-    const uint64_t tk = s.next_ticket++;
-    s.reqs.emplace(tk, r);
+    const uint64_t tk = s.reqs.next_ticket();
+    s.reqs.add(r);
     s.pending.push_back(tk);
     ++s.submitted;
     if (!s.t_first)
         s.t_first = r.t_arrive;
     s.max_pending_seen = std::max<uint64_t>(s.max_pending_seen, s.pending.size());
-    *ticket = tk;
+    return tk;
+}
+
+int submit_impl(uint32_t stream_id, uint64_t length, uint32_t flags, uint64_t *ticket, bool wait)
+{
+    Server &s = SV();
+    std::unique_lock<std::mutex> lk(s.mu);
+    clear_error();
+    if (!ticket)
+        return set_error(RNGX_E_INVAL, "serve: ticket is NULL");
+    int rc = check_request_locked(s, stream_id, length, flags);
+    if (rc == RNGX_OK)
+        rc = make_room_locked(s, lk, wait);
+    if (rc)
+        return rc;
+    *ticket = enqueue_locked(s, stream_id, length, flags);
+    s.submit_seq.fetch_add(1, std::memory_order_release);
+    s.cv_work.notify_one();
+    return RNGX_OK;
+}
+
+// Submit k requests under one lock acquisition (tickets optional).
+int submit_many_impl(const uint32_t *ids, const uint64_t *lengths, uint64_t k, uint32_t flags,
+                     uint64_t *tickets)
+{
+    Server &s = SV();
+    std::unique_lock<std::mutex> lk(s.mu);
+    for (uint64_t i = 0; i < k; ++i) {
+        int rc = check_request_locked(s, ids[i], lengths[i], flags);
+        if (rc == RNGX_OK)
+            rc = make_room_locked(s, lk, true);
+        if (rc)
+            return rc;
+        const uint64_t tk = enqueue_locked(s, ids[i], lengths[i], flags);
+        if (tickets)
+            tickets[i] = tk;
+    }
+    s.submit_seq.fetch_add(1, std::memory_order_release);
     s.cv_work.notify_one();
     return RNGX_OK;
 }
@@ -416,16 +467,17 @@ void stop_locked(Server &s, std::unique_lock<std::mutex> &lk)
         s.worker.join();
         lk.lock();
     }
-    for (Flight &f : s.flights) {
+    for (Flight &f : s.flights)
         release_slot(f.slot);
-        if (f.stream)
-            (void)hipStreamDestroy(f.stream);
-    }
     s.flights.clear();
+    for (hipStream_t st : s.streams)
+        if (st)
+            (void)hipStreamDestroy(st);
+    s.streams.clear();
     if (s.d_states)
         (void)hipFree(s.d_states);
     s.d_states = nullptr;
-    s.reqs.clear();
+    s.reqs.clear(s.reqs.next_ticket()); // tickets stay unique across restarts
     s.pending.clear();
     s.admitted.clear();
     s.cursor.clear();
@@ -471,17 +523,22 @@ extern "C" int rngx_serve_start(uint64_t seed, uint32_t n_states, void *pool, ui
     if (e != hipSuccess)
         return hip_fail(e, "serve: hipMalloc (resident states)");
     s.d_states = static_cast<uint64_t *>(p);
-    s.flights.resize(n_streams);
-    for (Flight &f : s.flights) {
-        e = hipStreamCreateWithFlags(&f.stream, hipStreamNonBlocking);
+    s.streams.assign(n_streams, nullptr);
+    for (hipStream_t &st : s.streams) {
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
         if (e != hipSuccess) {
             rc = hip_fail(e, "serve: hipStreamCreate");
             break;
         }
     }
+    s.flights.resize((size_t)n_streams * SLOTS_PER_STREAM);
+    for (size_t i = 0; i < s.flights.size(); ++i) {
+        s.flights[i].stream_index = (uint32_t)(i % n_streams);
+        s.flights[i].stream = s.streams[i % n_streams];
+    }
     if (rc == RNGX_OK) {
         // The resident base states: the init kernel, once.
-        hipStream_t s0 = s.flights[0].stream;
+        hipStream_t s0 = s.streams[0];
         const int tok = prof::begin("INIT_KERNEL", s0);
         e = launch_init(s.d_states, n_states, seed_mix(seed), s0);
         prof::end(tok, s0);
@@ -491,9 +548,10 @@ extern "C" int rngx_serve_start(uint64_t seed, uint32_t n_states, void *pool, ui
             rc = hip_fail(e, "serve: init kernel");
     }
     if (rc) {
-        for (Flight &f : s.flights)
-            if (f.stream)
-                (void)hipStreamDestroy(f.stream);
+        for (hipStream_t st : s.streams)
+            if (st)
+                (void)hipStreamDestroy(st);
+        s.streams.clear();
         s.flights.clear();
         (void)hipFree(s.d_states);
         s.d_states = nullptr;
@@ -511,7 +569,6 @@ extern "C" int rngx_serve_start(uint64_t seed, uint32_t n_states, void *pool, ui
     s.cfg.use_graph = 0; // batch sizes vary: launch directly with a fitted grid
     s.worker_rc = RNGX_OK;
     s.worker_msg.clear();
-    s.next_ticket = 1;
     reset_stats_locked(s);
     s.active = true;
     s.stopping = false;
@@ -531,6 +588,15 @@ extern "C" int rngx_serve_try_submit(uint32_t stream_id, uint64_t length, uint32
     return submit_impl(stream_id, length, flags, ticket, false);
 }
 
+extern "C" int rngx_serve_submit_many(const uint32_t *stream_ids, const uint64_t *lengths,
+                                      uint64_t k, uint32_t flags, uint64_t *tickets)
+{
+    clear_error();
+    if (k && (!stream_ids || !lengths))
+        return set_error(RNGX_E_INVAL, "serve: NULL request arrays");
+    return submit_many_impl(stream_ids, lengths, k, flags, tickets);
+}
+
 extern "C" int rngx_serve_poll(uint64_t ticket, uint64_t **values, int *done)
 {
     Server &s = SV();
@@ -538,11 +604,11 @@ extern "C" int rngx_serve_poll(uint64_t ticket, uint64_t **values, int *done)
     clear_error();
     if (!s.active)
         return set_error(RNGX_E_NOINIT, "serve: the server is not running");
-    auto it = s.reqs.find(ticket);
-    if (it == s.reqs.end())
+    const SReq *rp = s.reqs.find(ticket);
+    if (!rp)
         return set_error(RNGX_E_INVAL, "serve: unknown or released ticket %llu",
                          (unsigned long long)ticket);
-    const SReq &r = it->second;
+    const SReq &r = *rp;
     if (done)
         *done = r.state == ST_DONE;
     if (values)
@@ -561,13 +627,13 @@ extern "C" int rngx_serve_wait(uint64_t ticket, double timeout_s, uint64_t **val
     for (;;) {
         if (!s.active)
             return set_error(RNGX_E_NOINIT, "serve: the server is not running");
-        auto it = s.reqs.find(ticket);
-        if (it == s.reqs.end())
+        const SReq *rp = s.reqs.find(ticket);
+        if (!rp)
             return set_error(RNGX_E_INVAL, "serve: unknown or released ticket %llu",
                              (unsigned long long)ticket);
-        if (it->second.state == ST_DONE) {
+        if (rp->state == ST_DONE) {
             if (values)
-                *values = reinterpret_cast<uint64_t *>(s.pool + it->second.pool_off);
+                *values = reinterpret_cast<uint64_t *>(s.pool + rp->pool_off);
             return RNGX_OK;
         }
         if (s.worker_rc)
@@ -585,16 +651,17 @@ extern "C" int rngx_serve_release(uint64_t ticket)
     clear_error();
     if (!s.active)
         return set_error(RNGX_E_NOINIT, "serve: the server is not running");
-    auto it = s.reqs.find(ticket);
-    if (it == s.reqs.end())
+    SReq *rp = s.reqs.find(ticket);
+    if (!rp)
         return set_error(RNGX_E_INVAL, "serve: unknown or released ticket %llu",
                          (unsigned long long)ticket);
-    if (it->second.state != ST_DONE)
+    if (rp->state != ST_DONE)
         return set_error(RNGX_E_BUSY, "serve: ticket %llu is not done yet",
                          (unsigned long long)ticket);
-    s.alloc.release(it->second.pool_off);
+    s.alloc.release(rp->pool_seq);
     ++s.released;
-    s.reqs.erase(it);
+    s.reqs.erase(ticket);
+    s.submit_seq.fetch_add(1, std::memory_order_release);
     s.cv_work.notify_one(); // memory freed: admission may proceed
     return RNGX_OK;
 }
@@ -637,16 +704,24 @@ extern "C" int rngx_serve_run_trace(const double *arrival_s, const uint32_t *str
             return set_error(RNGX_E_NOINIT, "serve: the server is not running");
         reset_stats_locked(s);
     }
-    const auto t0 = Clock::now();
-    for (uint64_t i = 0; i < k; ++i) {
-        const auto due = t0 + std::chrono::duration_cast<Clock::duration>(
-                                  std::chrono::duration<double>(arrival_s[i]));
-        while (Clock::now() < due) {
+    const uint64_t t0 = now_ns();
+    uint64_t i = 0;
+    while (i < k) {
+        const uint64_t due = t0 + (uint64_t)(arrival_s[i] * 1e9);
+        uint64_t t = now_ns();
+        while (t < due) {
+            __builtin_ia32_pause();
+            t = now_ns();
         }
-        uint64_t tk = 0;
-        const int rc = submit_impl(stream_id[i], length[i], RNGX_SERVE_AUTORELEASE, &tk, true);
+        // Every request whose arrival time has passed goes in one submission.
+        uint64_t j = i + 1;
+        while (j < k && t0 + (uint64_t)(arrival_s[j] * 1e9) <= t)
+            ++j;
+        const int rc = submit_many_impl(stream_id + i, length + i, j - i, RNGX_SERVE_AUTORELEASE,
+                                        nullptr);
         if (rc)
             return rc;
+        i = j;
     }
     Server &s = SV();
     std::unique_lock<std::mutex> lk(s.mu);

@@ -39,7 +39,8 @@ class RngxError(RuntimeError):
 
 class BatchCfg(ctypes.Structure):
     _fields_ = [("values_per_lane", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
-                ("blocks", ctypes.c_uint32), ("use_graph", ctypes.c_uint32)]
+                ("blocks", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
+                ("row_values", ctypes.c_uint32)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -49,7 +50,7 @@ class TuneEntry(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("best", BatchCfg), ("best_ms", ctypes.c_double), ("best_gbs", ctypes.c_double),
                 ("n_tried", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("tried", TuneEntry * 64)]
+                ("tried", TuneEntry * 128)]
 
 
 class ServeReport(ctypes.Structure):
@@ -58,7 +59,8 @@ class ServeReport(ctypes.Structure):
                                                 "bytes")] + \
                [(k, ctypes.c_double) for k in ("elapsed_s", "gbs", "lat_p50_us", "lat_p99_us",
                                                 "lat_max_us", "lat_mean_us", "wait_p50_us",
-                                                "wait_p99_us")] + \
+                                                "wait_p99_us", "launch_p50_us", "launch_p99_us",
+                                                "exec_p50_us", "exec_p99_us")] + \
                [("max_pending", ctypes.c_uint64), ("admission_stalls", ctypes.c_uint64),
                 ("mean_batch_requests", ctypes.c_double), ("pool_bytes", ctypes.c_uint64),
                 ("pool_used_bytes", ctypes.c_uint64), ("pool_peak_bytes", ctypes.c_uint64)]
@@ -120,6 +122,7 @@ _SIGS = {
     "rngx_serve_start": ([_u64, _u32, _p, _u64, _u32, _u32], _int),
     "rngx_serve_submit": ([_u32, _u64, _u32, ctypes.POINTER(_u64)], _int),
     "rngx_serve_try_submit": ([_u32, _u64, _u32, ctypes.POINTER(_u64)], _int),
+    "rngx_serve_submit_many": ([_p, _p, _u64, _u32, _p], _int),
     "rngx_serve_poll": ([_u64, ctypes.POINTER(_p), ctypes.POINTER(_int)], _int),
     "rngx_serve_wait": ([_u64, ctypes.c_double, ctypes.POINTER(_p)], _int),
     "rngx_serve_release": ([_u64], _int),
@@ -301,21 +304,21 @@ def generate_batch(reqs, out, stream=None):
     return total
 
 
-def set_batch_cfg(values_per_lane=256, waves_per_block=4, blocks=0, use_graph=True):
-    cfg = BatchCfg(values_per_lane, waves_per_block, blocks, int(bool(use_graph)))
+def set_batch_cfg(values_per_lane=256, waves_per_block=4, blocks=0, use_graph=True,
+                  row_values=16):
+    cfg = BatchCfg(values_per_lane, waves_per_block, blocks, int(bool(use_graph)), row_values)
     _check(lib().rngx_set_batch_cfg(ctypes.byref(cfg)))
 
 
 def get_batch_cfg():
     c = BatchCfg()
     _check(lib().rngx_get_batch_cfg(ctypes.byref(c)))
-    return {"values_per_lane": c.values_per_lane, "waves_per_block": c.waves_per_block,
-            "blocks": c.blocks, "use_graph": bool(c.use_graph)}
+    return _cfg_dict(c)
 
 
 def _cfg_dict(c):
     return {"values_per_lane": c.values_per_lane, "waves_per_block": c.waves_per_block,
-            "blocks": c.blocks, "use_graph": bool(c.use_graph)}
+            "blocks": c.blocks, "use_graph": bool(c.use_graph), "row_values": c.row_values}
 
 
 def autotune_batch(reqs, out, reps=2, stream=None):
@@ -326,7 +329,7 @@ def autotune_batch(reqs, out, reps=2, stream=None):
     res = TuneResult()
     _check(lib().rngx_autotune_batch(ptr, len(reqs), optr, out.numel(), reps,
                                      stream_handle(stream), ctypes.byref(res)))
-    n = min(res.n_tried, 64)
+    n = min(res.n_tried, 128)
     return {"best": _cfg_dict(res.best), "best_ms": res.best_ms, "best_gbs": res.best_gbs,
             "tried": [(_cfg_dict(res.tried[i].cfg), res.tried[i].ms) for i in range(n)]}
 
@@ -370,6 +373,19 @@ def serve_submit(stream_id: int, length: int, autorelease: bool = False, wait: b
     f = lib().rngx_serve_submit if wait else lib().rngx_serve_try_submit
     _check(f(stream_id, length, SERVE_AUTORELEASE if autorelease else 0, ctypes.byref(t)))
     return t.value
+
+
+def serve_submit_many(stream_ids, lengths, autorelease: bool = False):
+    """Submit many requests at once; returns their tickets (numpy uint64)."""
+    import numpy as np
+    g = np.ascontiguousarray(stream_ids, dtype=np.uint32)
+    n = np.ascontiguousarray(lengths, dtype=np.uint64)
+    if len(g) != len(n):
+        raise ValueError("stream_ids and lengths differ in length")
+    t = np.zeros(len(g), dtype=np.uint64)
+    _check(lib().rngx_serve_submit_many(g.ctypes.data, n.ctypes.data, len(g),
+                                        SERVE_AUTORELEASE if autorelease else 0, t.ctypes.data))
+    return t
 
 
 def serve_poll(ticket: int):

@@ -147,12 +147,12 @@ def test_batch_argument_errors_without_gpu():
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, None, 3, None) == rngx.RNGX_E_INVAL
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, None, 4, None) == rngx.RNGX_E_INVAL
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, 8, 4, None) == rngx.RNGX_E_INVAL  # misaligned
-    assert L.rngx_set_batch_cfg(ctypes.byref(rngx.BatchCfg(100, 4, 0, 1))) == rngx.RNGX_E_INVAL
-    assert L.rngx_set_batch_cfg(ctypes.byref(rngx.BatchCfg(256, 5, 0, 1))) == rngx.RNGX_E_INVAL
-    assert L.rngx_set_batch_cfg(ctypes.byref(rngx.BatchCfg(256, 4, 70000, 1))) == rngx.RNGX_E_INVAL
-    rngx.set_batch_cfg(512, 2, 100, False)
+    for bad in [(100, 4, 0, 1, 16), (256, 5, 0, 1, 16), (256, 4, 70000, 1, 16),
+                (256, 4, 0, 2, 16), (256, 4, 0, 1, 12)]:
+        assert L.rngx_set_batch_cfg(ctypes.byref(rngx.BatchCfg(*bad))) == rngx.RNGX_E_INVAL, bad
+    rngx.set_batch_cfg(512, 2, 100, False, 8)
     assert rngx.get_batch_cfg() == {"values_per_lane": 512, "waves_per_block": 2, "blocks": 100,
-                                    "use_graph": False}
+                                    "use_graph": False, "row_values": 8}
     rngx.set_batch_cfg()
 
 
@@ -168,3 +168,15 @@ def test_serve_calls_before_start_are_noinit():
     assert L.rngx_serve_start(1, 0, 4096, 1 << 16, 4, 16) == rngx.RNGX_E_INVAL
     assert L.rngx_serve_start(1, 10, 4096 + 8, 1 << 16, 4, 16) == rngx.RNGX_E_INVAL
     assert L.rngx_serve_set_max_pending(0) == rngx.RNGX_E_INVAL
+
+
+def test_server_pool_ring_and_ticket_table_model(tmp_path):
+    import subprocess
+    src = os.path.join(ROOT, "tests", "helpers", "pool_model.cpp")
+    exe = str(tmp_path / "pool_model")
+    # Host-only code: built with g++ and the address/undefined-behaviour sanitizers.
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-Wall", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all", "-I",
+                    os.path.join(ROOT, "paper_1609_01257_amd", "csrc"), src, "-o", exe], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr

@@ -57,6 +57,23 @@ def test_results_follow_the_cursor_rule(oracle, server):
     assert st["pool_used_bytes"] == 0
 
 
+def test_submit_many_matches_single_submissions(oracle, server):
+    seed = 31
+    pool = server(seed, 50, 256 << 20)
+    hist = _history(3, 120, 50, 20000)
+    tickets = rngx.serve_submit_many([g for g, _ in hist], [L for _, L in hist])
+    assert len(set(tickets.tolist())) == len(hist)
+    exp = oracle.serve_expected(seed, hist)
+    for t, (g, L), e in zip(tickets, hist, exp):
+        assert np.array_equal(_values(pool, rngx.serve_wait(int(t), 30.0), L), e)
+        rngx.serve_release(int(t))
+    # An invalid request stops the submission there; earlier ones went in.
+    with pytest.raises(rngx.RngxError):
+        rngx.serve_submit_many([1, 2, 50, 3], [10, 10, 10, 10])
+    st = rngx.serve_stats()
+    assert st["submitted"] == len(hist) + 2
+
+
 def test_alone_and_in_the_mix_are_identical(oracle, server):
     seed, n_states = 99, 64
     hist = _history(1, 400, n_states, 100000)
