@@ -204,14 +204,17 @@ int rngx_generate_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_
                         void *stream);
 
 /* Launch configuration of the batched kernel.
- * values_per_lane: S, values each lane produces per work item (64, 128,
- *   256, 512 or 1024); a work item is a tile of 64 * S output values.
+ * values_per_lane: S, values each lane produces per work item (16, 32, 64,
+ *   128, 256, 512 or 1024); a work item is a tile of 64 * S output values.
  * waves_per_block: 1..4; blocks: 1..65536 (the persistent grid);
  * use_graph: 1 to capture the table upload and the launch in a HIP graph
  *   once and replay it, 0 to launch directly;
  * row_values: values each lane stages in LDS per round before the wave
  *   writes them out (8: 64-byte rows, 5 KiB of LDS per wave; 16: 128-byte
- *   rows, 9 KiB per wave).
+ *   rows, 9 KiB per wave);
+ * run_items: 0..64, work items a wave takes at once (0 means 1); within a
+ *   run, a wave moving to the next tile of the same request carries each
+ *   lane's state forward instead of jumping from the stream's start.
  * The output never depends on the configuration. */
 typedef struct rngx_batch_cfg {
     uint32_t values_per_lane;
@@ -219,6 +222,7 @@ typedef struct rngx_batch_cfg {
     uint32_t blocks;
     uint32_t use_graph;
     uint32_t row_values;
+    uint32_t run_items;
 } rngx_batch_cfg;
 
 int rngx_set_batch_cfg(const rngx_batch_cfg *cfg);

@@ -21,11 +21,12 @@ namespace rngx {
 
 namespace {
 
-const uint32_t kValuesPerLane[5] = {64, 128, 256, 512, 1024};
+const uint32_t kValuesPerLane[7] = {16, 32, 64, 128, 256, 512, 1024};
+constexpr int kNumS = 7;
 
 int s_index(uint32_t s)
 {
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < kNumS; ++i)
         if (kValuesPerLane[i] == s)
             return i;
     return -1;
@@ -36,10 +37,11 @@ struct BatchGlobals {
     int device = -1;
     int n_cus = 0;
     uint64_t *d_pow2 = nullptr;   // 64 matrices x 64 rows
-    uint64_t *d_rows_s = nullptr; // T^S rows for each allowed S (5 x 64)
+    uint64_t *d_rows_s = nullptr;     // T^S rows for each allowed S (kNumS x 64)
+    uint64_t *d_cols_carry = nullptr; // T^(63 S) columns for each allowed S (kNumS x 64)
     uint64_t *d_acc = nullptr;    // checksum accumulator
     uint64_t *h_acc = nullptr;    // page-locked copy of it
-    rngx_batch_cfg cfg{256, 4, 0, 1, 16};
+    rngx_batch_cfg cfg{256, 4, 0, 1, 16, 1};
     BatchSlot api_slot;
 };
 
@@ -68,7 +70,8 @@ void free_slot(BatchSlot &s)
 
 } // namespace
 
-int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus)
+int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus,
+                        const uint64_t **cols_carry_all)
 {
     // Own lock: the server thread reaches here without the batch API lock.
     static std::mutex tables_mu;
@@ -81,21 +84,34 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int 
             (void)hipFree(g.d_pow2);
         if (g.d_rows_s)
             (void)hipFree(g.d_rows_s);
+        if (g.d_cols_carry)
+            (void)hipFree(g.d_cols_carry);
         if (g.d_acc)
             (void)hipFree(g.d_acc);
         if (g.h_acc)
             (void)hipHostFree(g.h_acc);
-        g.d_pow2 = g.d_rows_s = g.d_acc = g.h_acc = nullptr;
-        std::vector<uint64_t> rows(5 * 64);
-        for (int i = 0; i < 5; ++i)
+        g.d_pow2 = g.d_rows_s = g.d_cols_carry = g.d_acc = g.h_acc = nullptr;
+        std::vector<uint64_t> rows(kNumS * 64), cols(kNumS * 64, 0);
+        for (int i = 0; i < kNumS; ++i) {
             power_rows(kValuesPerLane[i], rows.data() + 64 * i);
+            // A lane that just emitted its S values of a tile is C - S = 63 S
+            // values short of its start in the next tile.
+            uint64_t carry_rows[64];
+            power_rows(63ull * kValuesPerLane[i], carry_rows);
+            for (int r = 0; r < 64; ++r)
+                for (int j = 0; j < 64; ++j)
+                    cols[64 * i + j] |= ((carry_rows[r] >> j) & 1u) << r;
+        }
         RNGX_HIP(hipMalloc(&g.d_pow2, 64 * 64 * sizeof(uint64_t)));
         RNGX_HIP(hipMalloc(&g.d_rows_s, rows.size() * sizeof(uint64_t)));
+        RNGX_HIP(hipMalloc(&g.d_cols_carry, cols.size() * sizeof(uint64_t)));
         RNGX_HIP(hipMalloc(&g.d_acc, sizeof(uint64_t)));
         RNGX_HIP(hipHostMalloc(&g.h_acc, sizeof(uint64_t), hipHostMallocDefault));
         RNGX_HIP(hipMemcpy(g.d_pow2, jump_tables(), 64 * 64 * sizeof(uint64_t),
                            hipMemcpyHostToDevice));
         RNGX_HIP(hipMemcpy(g.d_rows_s, rows.data(), rows.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice));
+        RNGX_HIP(hipMemcpy(g.d_cols_carry, cols.data(), cols.size() * sizeof(uint64_t),
                            hipMemcpyHostToDevice));
         RNGX_HIP(hipDeviceGetAttribute(&g.n_cus, hipDeviceAttributeMultiprocessorCount, dev));
         g.device = dev;
@@ -104,6 +120,8 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int 
         *pow2 = g.d_pow2;
     if (rows_s_all)
         *rows_s_all = g.d_rows_s;
+    if (cols_carry_all)
+        *cols_carry_all = g.d_cols_carry;
     if (n_cus)
         *n_cus = g.n_cus;
     return RNGX_OK;
@@ -234,9 +252,9 @@ int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out
 int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stream,
                  bool fit_grid, const char *prof_name)
 {
-    const uint64_t *pow2 = nullptr, *rows_all = nullptr;
+    const uint64_t *pow2 = nullptr, *rows_all = nullptr, *cols_all = nullptr;
     int n_cus = 0;
-    int rc = batch_tables_locked(&pow2, &rows_all, &n_cus);
+    int rc = batch_tables_locked(&pow2, &rows_all, &n_cus, &cols_all);
     if (rc)
         return rc;
     rngx_batch_cfg cfg = resolved_cfg(cfg_in, n_cus);
@@ -245,14 +263,18 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
         if (need < cfg.blocks)
             cfg.blocks = (uint32_t)std::max<uint64_t>(1, need);
     }
-    const uint64_t *rows_s = rows_all + 64 * s_index(cfg.values_per_lane);
+    BatchTables tabs;
+    tabs.pow2 = pow2;
+    tabs.rows_s = rows_all + 64 * s_index(cfg.values_per_lane);
+    tabs.cols_carry = cols_all + 64 * s_index(cfg.values_per_lane);
     const BatchDesc *ddesc = static_cast<const BatchDesc *>(slot.devtab);
     const int tok = prof::begin(prof_name, stream);
     if (cfg.use_graph) {
         const bool same = slot.exec && slot.exec_cfg.values_per_lane == cfg.values_per_lane &&
                           slot.exec_cfg.waves_per_block == cfg.waves_per_block &&
                           slot.exec_cfg.blocks == cfg.blocks &&
-                          slot.exec_cfg.row_values == cfg.row_values;
+                          slot.exec_cfg.row_values == cfg.row_values &&
+                          slot.exec_cfg.run_items == cfg.run_items;
         if (!same) {
             if (slot.exec) {
                 (void)hipGraphExecDestroy(slot.exec);
@@ -264,7 +286,7 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
             RNGX_HIP(hipStreamBeginCapture(slot.cap_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e1 = hipMemcpyAsync(slot.devtab, slot.staging, bytes,
                                            hipMemcpyHostToDevice, slot.cap_stream);
-            hipError_t e2 = launch_batch(cfg, ddesc, pow2, rows_s, slot.cap_stream);
+            hipError_t e2 = launch_batch(cfg, ddesc, tabs, slot.cap_stream);
             hipGraph_t graph = nullptr;
             hipError_t e3 = hipStreamEndCapture(slot.cap_stream, &graph);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
@@ -285,7 +307,7 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
     } else {
         const size_t bytes = sizeof(BatchDesc) + (size_t)slot.m_staged * sizeof(BatchReq);
         RNGX_HIP(hipMemcpyAsync(slot.devtab, slot.staging, bytes, hipMemcpyHostToDevice, stream));
-        hipError_t e = launch_batch(cfg, ddesc, pow2, rows_s, stream);
+        hipError_t e = launch_batch(cfg, ddesc, tabs, stream);
         if (e != hipSuccess)
             return hip_fail(e, "batch kernel launch");
     }
@@ -311,11 +333,13 @@ void release_batch()
         (void)hipFree(g.d_pow2);
     if (g.d_rows_s)
         (void)hipFree(g.d_rows_s);
+    if (g.d_cols_carry)
+        (void)hipFree(g.d_cols_carry);
     if (g.d_acc)
         (void)hipFree(g.d_acc);
     if (g.h_acc)
         (void)hipHostFree(g.h_acc);
-    g.d_pow2 = g.d_rows_s = g.d_acc = g.h_acc = nullptr;
+    g.d_pow2 = g.d_rows_s = g.d_cols_carry = g.d_acc = g.h_acc = nullptr;
     g.device = -1;
 }
 
@@ -361,7 +385,7 @@ extern "C" int rngx_set_batch_cfg(const rngx_batch_cfg *cfg)
         return set_error(RNGX_E_INVAL, "rngx_set_batch_cfg: values_per_lane must be 64, 128, "
                                        "256, 512 or 1024, waves_per_block 1..4, blocks "
                                        "0..65536 (0 = 16 waves per compute unit), use_graph 0/1, "
-                                       "row_values 8 or 16");
+                                       "row_values 8 or 16, run_items 0..64");
     g.cfg = *cfg;
     return RNGX_OK;
 }
@@ -440,6 +464,7 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
                 c.blocks = (uint32_t)std::max(1, n_cus * (int)waves_per_cu[oi] / (int)wpbs[wi]);
                 c.use_graph = g.cfg.use_graph;
                 c.row_values = rows[ri];
+                c.run_items = g.cfg.run_items;
                 rc = batch_stage(g.api_slot, reqs, m, out, out_cap, c.values_per_lane, &total);
                 if (rc)
                     return rc;

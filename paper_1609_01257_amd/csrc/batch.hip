@@ -69,20 +69,34 @@ __device__ __forceinline__ uint64_t wave_jump(const uint64_t *__restrict__ pow2,
 
 // Next work item for the wave: lane 0 bumps the counter with a (vector)
 // global atomic and the value is broadcast to the wave.
-__device__ __forceinline__ uint64_t next_item(unsigned long long *counter, uint32_t lane)
+__device__ __forceinline__ uint64_t next_item(unsigned long long *counter, uint32_t lane,
+                                              uint32_t count)
 {
     unsigned long long v = 0;
     if (lane == 0)
-        v = atomicAdd(counter, 1ull);
+        v = atomicAdd(counter, (unsigned long long)count);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
 }
 
+// y = M x for a lane's own x: XOR of the columns of M selected by x's bits.
+// The columns are wave-uniform (scalar loads); there is no cross-lane work.
+__device__ __forceinline__ uint64_t lane_matvec(const uint64_t *__restrict__ cols, uint64_t x)
+{
+    uint64_t y = 0;
+#pragma unroll 16
+    for (int j = 0; j < 64; ++j)
+        y ^= ((x >> j) & 1u) ? cols[j] : 0u;
+    return y;
+}
+
 template <int S, int R>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict__ desc,
                                                     const uint64_t *__restrict__ pow2,
-                                                    const uint64_t *__restrict__ rows_s)
+                                                    const uint64_t *__restrict__ rows_s,
+                                                    const uint64_t *__restrict__ cols_carry,
+                                                    uint32_t run_items)
 {
     constexpr uint64_t C = 64ull * S;
     constexpr int ROUND = R;
@@ -104,16 +118,34 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
     unsigned long long *counter =
         reinterpret_cast<unsigned long long *>(const_cast<uint64_t *>(&desc->next_item));
 
-    for (uint64_t item = next_item(counter, lane); item < n_items;
-         item = next_item(counter, lane)) {
-        // Request of this item: the last j with item_begin <= item.
-        uint32_t lo = 0, hi = m;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (reqs[mid].item_begin <= item)
-                lo = mid;
-            else
-                hi = mid;
+    // A wave takes runs of `run_items` consecutive items. While it stays on
+    // one request and the previous tile was full, every lane's state is
+    // already S values past its previous start and needs C - S more steps
+    // (one per-lane product with T^(C-S)): no search, jump or lane walk.
+    uint64_t item = 0, run_end = 0, req_end = 0;
+    uint32_t lo = 0;
+    bool carry = false;
+    uint64_t x = 0;
+    for (;;) {
+        if (item >= run_end) {
+            item = next_item(counter, lane, run_items);
+            if (item >= n_items)
+                break;
+            run_end = item + run_items < n_items ? item + run_items : n_items;
+            carry = false;
+        }
+        if (!carry) {
+            // Request of this item: the last j with item_begin <= item.
+            lo = 0;
+            uint32_t hi = m;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (reqs[mid].item_begin <= item)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            req_end = lo + 1 < m ? (uint64_t)reqs[lo + 1].item_begin : n_items;
         }
         g_req &r = reqs[lo];
         const uint64_t B = r.vbase, E = r.vbase + r.length;
@@ -121,33 +153,37 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
         g_u64 *__restrict__ obase =
             (g_u64 *)(reinterpret_cast<uintptr_t>(r.dst) - B * sizeof(uint64_t));
         const uint64_t T0 = (r.first_tile + (item - r.item_begin)) * C;
-        const uint64_t offset = r.offset;
-        const uint32_t gid = r.gid;
-        const uint64_t q0 = T0 > B ? T0 : B;
 
-        // State at q0, then each active lane's first position.
-        SeedMix mix;
-        mix.mix_low = r.mix_low;
-        mix.mix_high = r.mix_high;
-        mix.zero_fix = r.zero_fix;
-        const uint64_t x0 = states ? states[gid] : init_state(mix, gid);
-        uint64_t cur = wave_jump(pow2, lane, x0, offset + (q0 - B));
-        uint64_t curpos = q0;
-        uint64_t x = 0;
-        for (uint32_t l = 0; l < 64; ++l) {
-            const uint64_t ls = T0 + (uint64_t)l * S;
-            const uint64_t p = ls > B ? ls : B;
-            const uint64_t e = (ls + S) < E ? (ls + S) : E;
-            if (p >= e)
-                continue;
-            const uint64_t delta = p - curpos;
-            if (delta == (uint64_t)S)
-                cur = wave_matvec(row_s, cur);
-            else if (delta)
-                cur = wave_jump(pow2, lane, cur, delta);
-            curpos = p;
-            if (lane == l)
-                x = cur;
+        if (carry) {
+            x = lane_matvec(cols_carry, x);
+        } else {
+            const uint64_t q0 = T0 > B ? T0 : B;
+            const uint64_t offset = r.offset;
+            const uint32_t gid = r.gid;
+            // State at q0, then each active lane's first position.
+            SeedMix mix;
+            mix.mix_low = r.mix_low;
+            mix.mix_high = r.mix_high;
+            mix.zero_fix = r.zero_fix;
+            const uint64_t x0 = states ? states[gid] : init_state(mix, gid);
+            uint64_t cur = wave_jump(pow2, lane, x0, offset + (q0 - B));
+            uint64_t curpos = q0;
+            x = 0;
+            for (uint32_t l = 0; l < 64; ++l) {
+                const uint64_t ls = T0 + (uint64_t)l * S;
+                const uint64_t p = ls > B ? ls : B;
+                const uint64_t e = (ls + S) < E ? (ls + S) : E;
+                if (p >= e)
+                    continue;
+                const uint64_t delta = p - curpos;
+                if (delta == (uint64_t)S)
+                    cur = wave_matvec(row_s, cur);
+                else if (delta)
+                    cur = wave_jump(pow2, lane, cur, delta);
+                curpos = p;
+                if (lane == l)
+                    x = cur;
+            }
         }
 
         const bool full = T0 >= B && T0 + C <= E;
@@ -209,22 +245,25 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        // Lane l now holds the state at T0 + l*S + S when the tile was full.
+        ++item;
+        carry = full && item < run_end && item < req_end;
     }
 }
 
 template <int S>
-hipError_t launch_batch_s(const BatchDesc *desc, const uint64_t *pow2, const uint64_t *rows_s,
-                          uint32_t blocks, uint32_t waves_per_block, uint32_t row_values,
+hipError_t launch_batch_s(const BatchDesc *desc, const BatchTables &t, const rngx_batch_cfg &c,
                           hipStream_t s)
 {
     const size_t lds_bytes =
-        (size_t)waves_per_block * 64 * lds_row(row_values) * sizeof(uint64_t);
-    if (row_values == 8)
-        batch_kernel<S, 8><<<dim3(blocks), dim3(64 * waves_per_block), lds_bytes, s>>>(
-            desc, pow2, rows_s);
+        (size_t)c.waves_per_block * 64 * lds_row(c.row_values) * sizeof(uint64_t);
+    const uint32_t run = c.run_items ? c.run_items : 1;
+    if (c.row_values == 8)
+        batch_kernel<S, 8><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
+            desc, t.pow2, t.rows_s, t.cols_carry, run);
     else
-        batch_kernel<S, 16><<<dim3(blocks), dim3(64 * waves_per_block), lds_bytes, s>>>(
-            desc, pow2, rows_s);
+        batch_kernel<S, 16><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
+            desc, t.pow2, t.rows_s, t.cols_carry, run);
     return hipGetLastError();
 }
 
@@ -257,32 +296,26 @@ hipError_t launch_checksum(const uint64_t *data, uint64_t n, uint64_t *acc, hipS
 
 bool batch_cfg_valid(const rngx_batch_cfg &c)
 {
-    const bool s_ok = c.values_per_lane == 64 || c.values_per_lane == 128 ||
+    const bool s_ok = c.values_per_lane == 16 || c.values_per_lane == 32 ||
+                      c.values_per_lane == 64 || c.values_per_lane == 128 ||
                       c.values_per_lane == 256 || c.values_per_lane == 512 ||
                       c.values_per_lane == 1024;
     return s_ok && c.waves_per_block >= 1 && c.waves_per_block <= MAX_WAVES_PER_BLOCK &&
-           c.blocks <= 65536 && c.use_graph <= 1 && (c.row_values == 8 || c.row_values == 16);
+           c.blocks <= 65536 && c.use_graph <= 1 && (c.row_values == 8 || c.row_values == 16) &&
+           c.run_items <= 64;
 }
 
-hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const uint64_t *pow2,
-                        const uint64_t *rows_s, hipStream_t s)
+hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const BatchTables &t,
+                        hipStream_t s)
 {
     switch (cfg.values_per_lane) {
-    case 64:
-        return launch_batch_s<64>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block,
-                                 cfg.row_values, s);
-    case 128:
-        return launch_batch_s<128>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block,
-                                 cfg.row_values, s);
-    case 256:
-        return launch_batch_s<256>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block,
-                                 cfg.row_values, s);
-    case 512:
-        return launch_batch_s<512>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block,
-                                 cfg.row_values, s);
-    default:
-        return launch_batch_s<1024>(desc, pow2, rows_s, cfg.blocks, cfg.waves_per_block,
-                                    cfg.row_values, s);
+    case 16: return launch_batch_s<16>(desc, t, cfg, s);
+    case 32: return launch_batch_s<32>(desc, t, cfg, s);
+    case 64: return launch_batch_s<64>(desc, t, cfg, s);
+    case 128: return launch_batch_s<128>(desc, t, cfg, s);
+    case 256: return launch_batch_s<256>(desc, t, cfg, s);
+    case 512: return launch_batch_s<512>(desc, t, cfg, s);
+    default: return launch_batch_s<1024>(desc, t, cfg, s);
     }
 }
 

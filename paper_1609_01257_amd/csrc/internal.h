@@ -132,8 +132,15 @@ struct BatchSlot {
 };
 
 bool batch_cfg_valid(const rngx_batch_cfg &c);
+// Device tables one batch launch needs, for its values-per-lane S.
+struct BatchTables {
+    const uint64_t *pow2;       // T^(2^b), b < 64: 64 rows each
+    const uint64_t *rows_s;     // rows of T^S
+    const uint64_t *cols_carry; // columns of T^(63 S) (next tile, same lane)
+};
 // Device copies of the jump tables for the current device (thread-safe).
-int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus);
+int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus,
+                        const uint64_t **cols_carry_all = nullptr);
 rngx_batch_cfg resolved_cfg(const rngx_batch_cfg &c, int n_cus);
 int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out,
                 uint64_t out_cap, uint32_t values_per_lane, uint64_t *total_out);
@@ -156,8 +163,8 @@ void release_batch();
 void release_server(); // serve.cpp: stop the server, free its resources
 rngx_batch_cfg current_batch_cfg();
 int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *result);
-hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const uint64_t *pow2,
-                        const uint64_t *rows_s, hipStream_t s);
+hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const BatchTables &t,
+                        hipStream_t s);
 // Checksum sum_i data[i] * (2 i + 1) mod 2^64 into *acc (device, pre-zeroed).
 hipError_t launch_checksum(const uint64_t *data, uint64_t n, uint64_t *acc, hipStream_t s);
 

@@ -94,7 +94,7 @@ struct Server {
     std::vector<hipStream_t> streams;
     uint32_t max_batch = 1024;
     uint64_t max_pending = 1u << 20;
-    rngx_batch_cfg cfg{256, 4, 0, 0, 16};
+    rngx_batch_cfg cfg{256, 4, 0, 0, 16, 1};
     std::thread worker;
     int worker_rc = RNGX_OK;
     std::string worker_msg;

@@ -40,7 +40,7 @@ class RngxError(RuntimeError):
 class BatchCfg(ctypes.Structure):
     _fields_ = [("values_per_lane", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
                 ("blocks", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
-                ("row_values", ctypes.c_uint32)]
+                ("row_values", ctypes.c_uint32), ("run_items", ctypes.c_uint32)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -305,8 +305,9 @@ def generate_batch(reqs, out, stream=None):
 
 
 def set_batch_cfg(values_per_lane=256, waves_per_block=4, blocks=0, use_graph=True,
-                  row_values=16):
-    cfg = BatchCfg(values_per_lane, waves_per_block, blocks, int(bool(use_graph)), row_values)
+                  row_values=16, run_items=1):
+    cfg = BatchCfg(values_per_lane, waves_per_block, blocks, int(bool(use_graph)), row_values,
+                   run_items)
     _check(lib().rngx_set_batch_cfg(ctypes.byref(cfg)))
 
 
@@ -318,7 +319,8 @@ def get_batch_cfg():
 
 def _cfg_dict(c):
     return {"values_per_lane": c.values_per_lane, "waves_per_block": c.waves_per_block,
-            "blocks": c.blocks, "use_graph": bool(c.use_graph), "row_values": c.row_values}
+            "blocks": c.blocks, "use_graph": bool(c.use_graph), "row_values": c.row_values,
+            "run_items": c.run_items}
 
 
 def autotune_batch(reqs, out, reps=2, stream=None):

@@ -147,12 +147,12 @@ def test_batch_argument_errors_without_gpu():
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, None, 3, None) == rngx.RNGX_E_INVAL
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, None, 4, None) == rngx.RNGX_E_INVAL
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, 8, 4, None) == rngx.RNGX_E_INVAL  # misaligned
-    for bad in [(100, 4, 0, 1, 16), (256, 5, 0, 1, 16), (256, 4, 70000, 1, 16),
-                (256, 4, 0, 2, 16), (256, 4, 0, 1, 12)]:
+    for bad in [(100, 4, 0, 1, 16, 1), (256, 5, 0, 1, 16, 1), (256, 4, 70000, 1, 16, 1),
+                (256, 4, 0, 2, 16, 1), (256, 4, 0, 1, 12, 1), (256, 4, 0, 1, 16, 65)]:
         assert L.rngx_set_batch_cfg(ctypes.byref(rngx.BatchCfg(*bad))) == rngx.RNGX_E_INVAL, bad
-    rngx.set_batch_cfg(512, 2, 100, False, 8)
+    rngx.set_batch_cfg(512, 2, 100, False, 8, 3)
     assert rngx.get_batch_cfg() == {"values_per_lane": 512, "waves_per_block": 2, "blocks": 100,
-                                    "use_graph": False, "row_values": 8}
+                                    "use_graph": False, "row_values": 8, "run_items": 3}
     rngx.set_batch_cfg()
 
 

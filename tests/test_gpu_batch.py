@@ -43,12 +43,12 @@ def test_small_ragged_tables(oracle, seed):
     assert np.array_equal(got, exp)
 
 
-@pytest.mark.parametrize("S,wpb,graph,row", list(itertools.product(
-    [64, 128, 256, 512, 1024], [1, 2, 4], [False, True], [8, 16])))
-def test_every_launch_config(oracle, S, wpb, graph, row):
-    r = inputs.ragged_requests(m=23, seed=99, max_len=40000, max_offset=5000)
+@pytest.mark.parametrize("S,wpb,graph,row,run", list(itertools.product(
+    [16, 32, 64, 128, 256, 512, 1024], [1, 2, 4], [False, True], [8, 16], [1, 3, 8])))
+def test_every_launch_config(oracle, S, wpb, graph, row, run):
+    r = inputs.ragged_requests(m=23, seed=99, max_len=400000, max_offset=5000)
     exp = oracle.generate_batch(_oracle_reqs(oracle, r))
-    rngx.set_batch_cfg(S, wpb, 37, graph, row)
+    rngx.set_batch_cfg(S, wpb, 37, graph, row, run)
     assert np.array_equal(_run(_reqs(r), r.total), exp)
 
 
@@ -59,8 +59,8 @@ def test_tiny_and_zero_length_requests(oracle):
                         np.arange(m, dtype=np.uint32) * 1000,
                         np.arange(m, dtype=np.uint64) * 7, np.array(lengths, dtype=np.uint64))
     exp = oracle.generate_batch(_oracle_reqs(oracle, r))
-    for graph, row in ((False, 16), (True, 8)):
-        rngx.set_batch_cfg(64, 1, 5, graph, row)
+    for graph, row, run in ((False, 16, 1), (True, 8, 4)):
+        rngx.set_batch_cfg(64, 1, 5, graph, row, run)
         assert np.array_equal(_run(_reqs(r), r.total), exp)
 
 
