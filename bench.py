@@ -245,19 +245,24 @@ def serving(torch, rngx, seconds, plain_gbs):
     return res
 
 
-def cpu_baseline(n_total, iters):
+def cpu_baseline(n_total, iters, min_seconds=10.0):
     """The CPU oracle, single-threaded, on the first 2^20 work-items of the
-    workload (all iterations)."""
+    workload (all iterations), repeated until at least `min_seconds` of CPU
+    work have been timed."""
     import oracle
     n = 1 << 20
-    t0 = time.perf_counter()
-    out = oracle.generate(1, n, iters)
-    dt = time.perf_counter() - t0
-    gbs = out.nbytes / dt / 1e9
-    del out
+    calls, dt, nbytes = 0, 0.0, 0
+    while dt < min_seconds:
+        t0 = time.perf_counter()
+        out = oracle.generate(1, n, iters)
+        dt += time.perf_counter() - t0
+        nbytes += out.nbytes
+        calls += 1
+        del out
+    gbs = nbytes / dt / 1e9
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d work-items x %d iterations (u64, %.1f GiB) in %.1f s"
-                      % (n, n_total, iters, n * iters * 8 / GIB, dt)}
+            "sample": "first %d of %d work-items x %d iterations (u64, %.1f GiB), computed "
+                      "%d times in %.1f s" % (n, n_total, iters, n * iters * 8 / GIB, calls, dt)}
 
 
 def main():
@@ -271,6 +276,8 @@ def main():
                     help="duration of each Poisson serving run (60 for the full runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline kernel (for profiling)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched ragged-stream step (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 16 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -293,6 +300,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log("copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
+        return
+    if args.batched_only:
+        res = batched(torch, rngx, args.steps)
+        log("batched:", res)
+        rngx.shutdown()
+        print(json.dumps({"batched": res}), flush=True)
         return
     n, iters, seed = 1 << 26, 256, 1
     log("headline: plain u64, n=2^26, iters=256, warmup=%d steps=%d" % (args.warmup, args.steps))

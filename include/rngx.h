@@ -88,6 +88,27 @@ int rngx_generate_u32(uint32_t n_iters, uint32_t *out, void *stream);
  * Errors: RNGX_E_NOINIT. */
 int rngx_info(uint64_t *seed, uint32_t *n_states, uint64_t *cursor);
 
+/* Checkpoint of the plain generator. Between generate calls the whole
+ * generator is its n_states 64-bit states plus the seed and the cursor: the
+ * state of work-item g is V(seed, g, cursor), the next value it emits (the
+ * rng kernel of Section 5 likewise keeps it in a buffer between launches).
+ * rngx_get_state waits for all queued work that uses the state, then copies
+ * the states into `states` (host memory, n entries, caller-owned) and
+ * returns seed and cursor (either pointer may be NULL).
+ * Errors: RNGX_E_NOINIT; RNGX_E_INVAL (states NULL, or n != n_states);
+ * RNGX_E_HIP. */
+int rngx_get_state(uint64_t *states, uint32_t n, uint64_t *seed, uint64_t *cursor);
+
+/* Resume from a checkpoint: replaces the generator (as rngx_init does, on
+ * the current device) by the n states read from `states` (host memory,
+ * copied before the call returns), labelled with `seed` and `cursor`.
+ * Generation then continues exactly where the checkpointed generator
+ * stopped. Starts a new profiling window, like rngx_init.
+ * Errors: RNGX_E_INVAL (states NULL, n == 0, or a state equal to 0, which
+ * xorshift maps to itself and no seeding produces); RNGX_E_NOMEM;
+ * RNGX_E_HIP. */
+int rngx_set_state(uint64_t seed, const uint64_t *states, uint32_t n, uint64_t cursor);
+
 /* Release the state buffer, events, streams and every other resource the
  * library holds (the constructor/destructor discipline of Section 4.1).
  * Safe to call when nothing is initialised. */
@@ -212,9 +233,10 @@ int rngx_generate_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_
  * row_values: values each lane stages in LDS per round before the wave
  *   writes them out (8: 64-byte rows, 5 KiB of LDS per wave; 16: 128-byte
  *   rows, 9 KiB per wave);
- * run_items: 0..64, work items a wave takes at once (0 means 1); within a
- *   run, a wave moving to the next tile of the same request carries each
- *   lane's state forward instead of jumping from the stream's start.
+ * run_items: 0..64, most work items a wave takes at once (0 means 1;
+ *   fewer near the end of the batch, down to 1); within a run, a wave
+ *   moving to the next tile of the same request carries each lane's state
+ *   forward instead of jumping from the stream's start.
  * The output never depends on the configuration. */
 typedef struct rngx_batch_cfg {
     uint32_t values_per_lane;
@@ -438,6 +460,30 @@ int rngx_profile_events(rngx_prof_event *out, uint32_t cap, uint32_t *n_out);
  * NULL with n > 0. */
 int rngx_profile_analyze(const rngx_prof_event *events, uint32_t n,
                          double elapsed_s, rngx_prof_stats *out);
+
+/* Export formats of an event table (Section 4.4: the profiler can write a
+ * table of queue name, start instant, end instant and event name to a text
+ * file for a queue-utilisation chart, as in Fig. 5).
+ * RNGX_EXPORT_TABLE: tab-separated text, a header line
+ *   "queue<TAB>t_start<TAB>t_end<TAB>event", then one line per event in order
+ *   of start time (ties: table order); instants in ns; queues are named
+ *   q0, q1, ... in order of their first event.
+ * RNGX_EXPORT_TRACE: Chrome trace-event JSON (one complete event per event,
+ *   one track per queue named as above, times in microseconds), which
+ *   Perfetto and chrome://tracing open. */
+#define RNGX_EXPORT_TABLE 0
+#define RNGX_EXPORT_TRACE 1
+
+/* Write a caller-supplied event table (host memory) to the file at `path`
+ * (created or truncated). Errors: RNGX_E_INVAL (path NULL, events NULL with
+ * n > 0, an event that ends before it starts, an unknown format, or the file
+ * cannot be written; rngx_last_error names the cause). */
+int rngx_profile_write(const rngx_prof_event *events, uint32_t n, const char *path, int format);
+
+/* Write the current window's event table (closing the window first if it is
+ * open). Errors: RNGX_E_NOINIT if no window was ever opened; otherwise as
+ * rngx_profile_write. */
+int rngx_profile_export(const char *path, int format);
 
 #ifdef __cplusplus
 }

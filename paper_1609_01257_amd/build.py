@@ -1,7 +1,8 @@
 """Build librngx.so (HIP for gfx950) in-tree with hipcc.
 
 Every source under csrc/ is compiled as HIP C++ for gfx950 and linked into
-paper_1609_01257_amd/librngx.so. Run ``python -m paper_1609_01257_amd.build``.
+paper_1609_01257_amd/librngx.so; cli/rngx_cli.cpp (host code only) becomes
+paper_1609_01257_amd/rngx_cli, linked against it. Run ``python -m paper_1609_01257_amd.build``.
 """
 from __future__ import annotations
 
@@ -16,6 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librngx.so")
+CLI_SRC = os.path.join(PKG, "cli", "rngx_cli.cpp")
+CLI = os.path.join(PKG, "rngx_cli")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -53,6 +56,14 @@ def build(extra=(), jobs: int = 8) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, LIB)
+    # The command-line program, linked against the library next to it.
+    tmp = CLI + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-O2", "-std=c++17", "-Wall", "-Wextra", "-I", os.path.join(ROOT, "include"),
+           CLI_SRC, "-o", tmp, "-L", PKG, "-lrngx", "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("rngx_cli build failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(tmp, CLI)
     return LIB
 
 

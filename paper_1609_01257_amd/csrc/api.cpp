@@ -5,11 +5,13 @@
 // `state_ready` event that orders every use of the state across caller
 // streams: a generate call makes its stream wait for `state_ready`,
 // launches, and re-records it.
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -57,6 +59,38 @@ int release_state_locked(Generator &c)
     c.n = 0;
     c.cursor = 0;
     return RNGX_OK;
+}
+
+// Free any previous state, make sure the library stream and event exist on
+// the current device, allocate n states and open a new profiling window.
+int fresh_state_locked(Generator &c, uint32_t n_states, const char *who)
+{
+    int rc = release_state_locked(c);
+    if (rc)
+        return rc;
+    int dev = -1;
+    RNGX_HIP(hipGetDevice(&dev));
+    if (c.lib_stream && dev != c.device) {
+        // Resources belong to another device: recreate them here.
+        (void)hipStreamDestroy(c.lib_stream);
+        (void)hipEventDestroy(c.state_ready);
+        c.lib_stream = nullptr;
+        c.state_ready = nullptr;
+    }
+    c.device = dev;
+    if (!c.lib_stream)
+        RNGX_HIP(hipStreamCreateWithFlags(&c.lib_stream, hipStreamNonBlocking));
+    if (!c.state_ready)
+        RNGX_HIP(hipEventCreateWithFlags(&c.state_ready, hipEventDisableTiming));
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, (size_t)n_states * sizeof(uint64_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(RNGX_E_NOMEM, "%s: cannot allocate %zu bytes of state: %s", who,
+                         (size_t)n_states * sizeof(uint64_t), hipGetErrorString(e));
+    }
+    c.state = static_cast<uint64_t *>(p);
+    return prof::start(c.lib_stream);
 }
 
 int generate_impl(uint32_t n_iters, void *out, void *stream, bool u32)
@@ -121,36 +155,11 @@ int rngx_init(uint64_t seed, uint32_t n_states)
     clear_error();
     if (n_states == 0)
         return set_error(RNGX_E_INVAL, "rngx_init: n_states must be at least 1");
-    int rc = release_state_locked(c);
-    if (rc)
-        return rc;
-    int dev = -1;
-    RNGX_HIP(hipGetDevice(&dev));
-    if (c.lib_stream && dev != c.device) {
-        // Resources belong to another device: recreate them here.
-        (void)hipStreamDestroy(c.lib_stream);
-        (void)hipEventDestroy(c.state_ready);
-        c.lib_stream = nullptr;
-        c.state_ready = nullptr;
-    }
-    c.device = dev;
-    if (!c.lib_stream)
-        RNGX_HIP(hipStreamCreateWithFlags(&c.lib_stream, hipStreamNonBlocking));
-    if (!c.state_ready)
-        RNGX_HIP(hipEventCreateWithFlags(&c.state_ready, hipEventDisableTiming));
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, (size_t)n_states * sizeof(uint64_t));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return set_error(RNGX_E_NOMEM, "rngx_init: cannot allocate %zu bytes of state: %s",
-                         (size_t)n_states * sizeof(uint64_t), hipGetErrorString(e));
-    }
-    c.state = static_cast<uint64_t *>(p);
-    rc = prof::start(c.lib_stream);
+    int rc = fresh_state_locked(c, n_states, "rngx_init");
     if (rc)
         return rc;
     const int tok = prof::begin("INIT_KERNEL", c.lib_stream);
-    e = launch_init(c.state, n_states, seed_mix(seed), c.lib_stream);
+    hipError_t e = launch_init(c.state, n_states, seed_mix(seed), c.lib_stream);
     prof::end(tok, c.lib_stream);
     if (e != hipSuccess)
         return hip_fail(e, "init kernel launch");
@@ -158,6 +167,53 @@ int rngx_init(uint64_t seed, uint32_t n_states)
     c.seed = seed;
     c.n = n_states;
     c.cursor = 0;
+    c.inited = true;
+    return RNGX_OK;
+}
+
+int rngx_get_state(uint64_t *states, uint32_t n, uint64_t *seed, uint64_t *cursor)
+{
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    clear_error();
+    if (!c.inited)
+        return set_error(RNGX_E_NOINIT, "rngx_get_state called before rngx_init");
+    if (!states || n != c.n)
+        return set_error(RNGX_E_INVAL, "rngx_get_state: need a host array of %u states", c.n);
+    int rc = check_device_locked(c);
+    if (rc)
+        return rc;
+    RNGX_HIP(hipStreamWaitEvent(c.lib_stream, c.state_ready, 0));
+    RNGX_HIP(hipMemcpyAsync(states, c.state, (size_t)n * sizeof(uint64_t),
+                            hipMemcpyDeviceToHost, c.lib_stream));
+    RNGX_HIP(hipStreamSynchronize(c.lib_stream));
+    if (seed)
+        *seed = c.seed;
+    if (cursor)
+        *cursor = c.cursor;
+    return RNGX_OK;
+}
+
+int rngx_set_state(uint64_t seed, const uint64_t *states, uint32_t n, uint64_t cursor)
+{
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    clear_error();
+    if (!states || n == 0)
+        return set_error(RNGX_E_INVAL, "rngx_set_state: need at least one state");
+    for (uint32_t g = 0; g < n; ++g)
+        if (states[g] == 0)
+            return set_error(RNGX_E_INVAL, "rngx_set_state: state %u is 0", g);
+    int rc = fresh_state_locked(c, n, "rngx_set_state");
+    if (rc)
+        return rc;
+    RNGX_HIP(hipMemcpyAsync(c.state, states, (size_t)n * sizeof(uint64_t),
+                            hipMemcpyHostToDevice, c.lib_stream));
+    RNGX_HIP(hipStreamSynchronize(c.lib_stream));
+    RNGX_HIP(hipEventRecord(c.state_ready, c.lib_stream));
+    c.seed = seed;
+    c.n = n;
+    c.cursor = cursor;
     c.inited = true;
     return RNGX_OK;
 }
@@ -295,6 +351,28 @@ int rngx_profile_analyze(const rngx_prof_event *events, uint32_t n, double elaps
 {
     clear_error();
     return analyze_table(events, n, elapsed_s, out);
+}
+
+int rngx_profile_write(const rngx_prof_event *events, uint32_t n, const char *path, int format)
+{
+    clear_error();
+    return write_table(events, n, path, format);
+}
+
+int rngx_profile_export(const char *path, int format)
+{
+    clear_error();
+    uint32_t n = 0;
+    int rc = prof::events(nullptr, 0, &n);
+    if (rc)
+        return rc;
+    std::vector<rngx_prof_event> ev(n);
+    uint32_t got = 0;
+    rc = prof::events(ev.data(), n, &got);
+    if (rc)
+        return rc;
+    ev.resize(std::min(n, got));
+    return write_table(ev.data(), (uint32_t)ev.size(), path, format);
 }
 
 } // extern "C"

@@ -38,7 +38,7 @@ struct BatchGlobals {
     int n_cus = 0;
     uint64_t *d_pow2 = nullptr;   // 64 matrices x 64 rows
     uint64_t *d_rows_s = nullptr;     // T^S rows for each allowed S (kNumS x 64)
-    uint64_t *d_cols_carry = nullptr; // T^(63 S) columns for each allowed S (kNumS x 64)
+    uint64_t *d_carry_nib = nullptr; // T^(63 S) nibble tables for each allowed S (kNumS x 256)
     uint64_t *d_acc = nullptr;    // checksum accumulator
     uint64_t *h_acc = nullptr;    // page-locked copy of it
     rngx_batch_cfg cfg{256, 4, 0, 1, 16, 1};
@@ -71,7 +71,7 @@ void free_slot(BatchSlot &s)
 } // namespace
 
 int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus,
-                        const uint64_t **cols_carry_all)
+                        const uint64_t **carry_nib_all)
 {
     // Own lock: the server thread reaches here without the batch API lock.
     static std::mutex tables_mu;
@@ -84,34 +84,43 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int 
             (void)hipFree(g.d_pow2);
         if (g.d_rows_s)
             (void)hipFree(g.d_rows_s);
-        if (g.d_cols_carry)
-            (void)hipFree(g.d_cols_carry);
+        if (g.d_carry_nib)
+            (void)hipFree(g.d_carry_nib);
         if (g.d_acc)
             (void)hipFree(g.d_acc);
         if (g.h_acc)
             (void)hipHostFree(g.h_acc);
-        g.d_pow2 = g.d_rows_s = g.d_cols_carry = g.d_acc = g.h_acc = nullptr;
-        std::vector<uint64_t> rows(kNumS * 64), cols(kNumS * 64, 0);
+        g.d_pow2 = g.d_rows_s = g.d_carry_nib = g.d_acc = g.h_acc = nullptr;
+        std::vector<uint64_t> rows(kNumS * 64), nib(kNumS * kCarryTable, 0);
         for (int i = 0; i < kNumS; ++i) {
             power_rows(kValuesPerLane[i], rows.data() + 64 * i);
             // A lane that just emitted its S values of a tile is C - S = 63 S
-            // values short of its start in the next tile.
+            // values short of its start in the next tile. M = T^(63 S) is
+            // stored as 16 tables of 16 entries: entry v of table q is
+            // M (v << 4q), so M x is the XOR of 16 lookups, one per nibble.
             uint64_t carry_rows[64];
             power_rows(63ull * kValuesPerLane[i], carry_rows);
+            uint64_t col[64] = {0};
             for (int r = 0; r < 64; ++r)
                 for (int j = 0; j < 64; ++j)
-                    cols[64 * i + j] |= ((carry_rows[r] >> j) & 1u) << r;
+                    col[j] |= ((carry_rows[r] >> j) & 1u) << r;
+            uint64_t *t = nib.data() + kCarryTable * i;
+            for (int q = 0; q < 16; ++q)
+                for (int v = 0; v < 16; ++v)
+                    for (int b = 0; b < 4; ++b)
+                        if ((v >> b) & 1)
+                            t[16 * q + v] ^= col[4 * q + b];
         }
         RNGX_HIP(hipMalloc(&g.d_pow2, 64 * 64 * sizeof(uint64_t)));
         RNGX_HIP(hipMalloc(&g.d_rows_s, rows.size() * sizeof(uint64_t)));
-        RNGX_HIP(hipMalloc(&g.d_cols_carry, cols.size() * sizeof(uint64_t)));
+        RNGX_HIP(hipMalloc(&g.d_carry_nib, nib.size() * sizeof(uint64_t)));
         RNGX_HIP(hipMalloc(&g.d_acc, sizeof(uint64_t)));
         RNGX_HIP(hipHostMalloc(&g.h_acc, sizeof(uint64_t), hipHostMallocDefault));
         RNGX_HIP(hipMemcpy(g.d_pow2, jump_tables(), 64 * 64 * sizeof(uint64_t),
                            hipMemcpyHostToDevice));
         RNGX_HIP(hipMemcpy(g.d_rows_s, rows.data(), rows.size() * sizeof(uint64_t),
                            hipMemcpyHostToDevice));
-        RNGX_HIP(hipMemcpy(g.d_cols_carry, cols.data(), cols.size() * sizeof(uint64_t),
+        RNGX_HIP(hipMemcpy(g.d_carry_nib, nib.data(), nib.size() * sizeof(uint64_t),
                            hipMemcpyHostToDevice));
         RNGX_HIP(hipDeviceGetAttribute(&g.n_cus, hipDeviceAttributeMultiprocessorCount, dev));
         g.device = dev;
@@ -120,8 +129,8 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int 
         *pow2 = g.d_pow2;
     if (rows_s_all)
         *rows_s_all = g.d_rows_s;
-    if (cols_carry_all)
-        *cols_carry_all = g.d_cols_carry;
+    if (carry_nib_all)
+        *carry_nib_all = g.d_carry_nib;
     if (n_cus)
         *n_cus = g.n_cus;
     return RNGX_OK;
@@ -252,9 +261,9 @@ int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out
 int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stream,
                  bool fit_grid, const char *prof_name)
 {
-    const uint64_t *pow2 = nullptr, *rows_all = nullptr, *cols_all = nullptr;
+    const uint64_t *pow2 = nullptr, *rows_all = nullptr, *nib_all = nullptr;
     int n_cus = 0;
-    int rc = batch_tables_locked(&pow2, &rows_all, &n_cus, &cols_all);
+    int rc = batch_tables_locked(&pow2, &rows_all, &n_cus, &nib_all);
     if (rc)
         return rc;
     rngx_batch_cfg cfg = resolved_cfg(cfg_in, n_cus);
@@ -266,7 +275,7 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
     BatchTables tabs;
     tabs.pow2 = pow2;
     tabs.rows_s = rows_all + 64 * s_index(cfg.values_per_lane);
-    tabs.cols_carry = cols_all + 64 * s_index(cfg.values_per_lane);
+    tabs.carry_nib = nib_all + kCarryTable * s_index(cfg.values_per_lane);
     const BatchDesc *ddesc = static_cast<const BatchDesc *>(slot.devtab);
     const int tok = prof::begin(prof_name, stream);
     if (cfg.use_graph) {
@@ -333,13 +342,13 @@ void release_batch()
         (void)hipFree(g.d_pow2);
     if (g.d_rows_s)
         (void)hipFree(g.d_rows_s);
-    if (g.d_cols_carry)
-        (void)hipFree(g.d_cols_carry);
+    if (g.d_carry_nib)
+        (void)hipFree(g.d_carry_nib);
     if (g.d_acc)
         (void)hipFree(g.d_acc);
     if (g.h_acc)
         (void)hipHostFree(g.h_acc);
-    g.d_pow2 = g.d_rows_s = g.d_cols_carry = g.d_acc = g.h_acc = nullptr;
+    g.d_pow2 = g.d_rows_s = g.d_carry_nib = g.d_acc = g.h_acc = nullptr;
     g.device = -1;
 }
 
@@ -455,8 +464,9 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
         for (uint32_t wi = 0; wi < 2; ++wi) {
             for (uint32_t oi = 0; oi < 3; ++oi) {
               for (uint32_t ri = 0; ri < 2; ++ri) {
-                const uint32_t lds_per_wave = 64 * (rows[ri] + 2) * 8;
-                if (waves_per_cu[oi] * lds_per_wave > 160u * 1024u)
+                const uint32_t lds_per_block =
+                    8u * (kCarryTable + wpbs[wi] * 64u * (rows[ri] + 2));
+                if (waves_per_cu[oi] / wpbs[wi] * lds_per_block > 160u * 1024u)
                     continue;
                 rngx_batch_cfg c;
                 c.values_per_lane = svals[si];

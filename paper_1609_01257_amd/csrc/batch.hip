@@ -80,14 +80,15 @@ __device__ __forceinline__ uint64_t next_item(unsigned long long *counter, uint3
     return ((uint64_t)hi << 32) | lo;
 }
 
-// y = M x for a lane's own x: XOR of the columns of M selected by x's bits.
-// The columns are wave-uniform (scalar loads); there is no cross-lane work.
-__device__ __forceinline__ uint64_t lane_matvec(const uint64_t *__restrict__ cols, uint64_t x)
+// y = M x for a lane's own x, M given as 16 tables of 16 entries (entry v of
+// table q is M (v << 4q)) held in LDS: the XOR of one lookup per nibble of x.
+// Each table spans 128 bytes, so the lanes' lookups never share a bank.
+__device__ __forceinline__ uint64_t lane_carry(const uint64_t *__restrict__ tab, uint64_t x)
 {
     uint64_t y = 0;
-#pragma unroll 16
-    for (int j = 0; j < 64; ++j)
-        y ^= ((x >> j) & 1u) ? cols[j] : 0u;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        y ^= tab[16 * q + (uint32_t)((x >> (4 * q)) & 15u)];
     return y;
 }
 
@@ -95,7 +96,7 @@ template <int S, int R>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict__ desc,
                                                     const uint64_t *__restrict__ pow2,
                                                     const uint64_t *__restrict__ rows_s,
-                                                    const uint64_t *__restrict__ cols_carry,
+                                                    const uint64_t *__restrict__ carry_nib,
                                                     uint32_t run_items)
 {
     constexpr uint64_t C = 64ull * S;
@@ -103,12 +104,17 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
     constexpr int LDS_ROW = lds_row(R);
     constexpr uint32_t CPR = R / 2;     // 16-byte chunks per row
     constexpr uint32_t RPI = 64 / CPR;  // rows per store instruction
-    extern __shared__ uint64_t lds_dyn[]; // 64 * LDS_ROW u64 per wave
+    // Dynamic LDS: the carry table, then 64 * LDS_ROW u64 per wave.
+    extern __shared__ uint64_t lds_dyn[];
     const uint32_t lane = threadIdx.x & 63u;
     // Wave index, made provably uniform so item bookkeeping runs on the
     // scalar unit and the request table is read with scalar loads.
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint64_t *lds = lds_dyn + (size_t)wid * 64 * LDS_ROW;
+    uint64_t *carry_tab = lds_dyn;
+    uint64_t *lds = lds_dyn + kCarryTable + (size_t)wid * 64 * LDS_ROW;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kCarryTable; i += blockDim.x)
+        carry_tab[i] = carry_nib[i];
+    __syncthreads();
 
     const uint64_t n_items = desc->n_items;
     const uint32_t m = desc->m;
@@ -122,16 +128,26 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
     // one request and the previous tile was full, every lane's state is
     // already S values past its previous start and needs C - S more steps
     // (one per-lane product with T^(C-S)): no search, jump or lane walk.
-    uint64_t item = 0, run_end = 0, req_end = 0;
+    // Runs shrink towards the end of the batch (guided self-scheduling: at
+    // most the items left, as last seen, over twice the number of waves), so
+    // the last runs taken do not leave a long tail.
+    const uint64_t n_waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    uint64_t item = 0, run_end = 0, req_end = 0, seen = 0;
     uint32_t lo = 0;
     bool carry = false;
     uint64_t x = 0;
     for (;;) {
         if (item >= run_end) {
-            item = next_item(counter, lane, run_items);
+            uint64_t want = 1;
+            if (run_items > 1) {
+                const uint64_t share = (n_items > seen ? n_items - seen : 0) / (2 * n_waves);
+                want = share < 1 ? 1 : (share < run_items ? share : run_items);
+            }
+            item = next_item(counter, lane, (uint32_t)want);
             if (item >= n_items)
                 break;
-            run_end = item + run_items < n_items ? item + run_items : n_items;
+            seen = item + want;
+            run_end = seen < n_items ? seen : n_items;
             carry = false;
         }
         if (!carry) {
@@ -155,7 +171,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
         const uint64_t T0 = (r.first_tile + (item - r.item_begin)) * C;
 
         if (carry) {
-            x = lane_matvec(cols_carry, x);
+            x = lane_carry(carry_tab, x);
         } else {
             const uint64_t q0 = T0 > B ? T0 : B;
             const uint64_t offset = r.offset;
@@ -256,14 +272,14 @@ hipError_t launch_batch_s(const BatchDesc *desc, const BatchTables &t, const rng
                           hipStream_t s)
 {
     const size_t lds_bytes =
-        (size_t)c.waves_per_block * 64 * lds_row(c.row_values) * sizeof(uint64_t);
+        (kCarryTable + (size_t)c.waves_per_block * 64 * lds_row(c.row_values)) * sizeof(uint64_t);
     const uint32_t run = c.run_items ? c.run_items : 1;
     if (c.row_values == 8)
         batch_kernel<S, 8><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
-            desc, t.pow2, t.rows_s, t.cols_carry, run);
+            desc, t.pow2, t.rows_s, t.carry_nib, run);
     else
         batch_kernel<S, 16><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
-            desc, t.pow2, t.rows_s, t.cols_carry, run);
+            desc, t.pow2, t.rows_s, t.carry_nib, run);
     return hipGetLastError();
 }
 

@@ -132,15 +132,17 @@ struct BatchSlot {
 };
 
 bool batch_cfg_valid(const rngx_batch_cfg &c);
+// Entries of the per-S carry table: 16 nibble positions x 16 values.
+constexpr int kCarryTable = 256;
 // Device tables one batch launch needs, for its values-per-lane S.
 struct BatchTables {
     const uint64_t *pow2;       // T^(2^b), b < 64: 64 rows each
     const uint64_t *rows_s;     // rows of T^S
-    const uint64_t *cols_carry; // columns of T^(63 S) (next tile, same lane)
+    const uint64_t *carry_nib; // T^(63 S) (next tile, same lane) as kCarryTable nibble entries
 };
 // Device copies of the jump tables for the current device (thread-safe).
 int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus,
-                        const uint64_t **cols_carry_all = nullptr);
+                        const uint64_t **carry_nib_all = nullptr);
 rngx_batch_cfg resolved_cfg(const rngx_batch_cfg &c, int n_cus);
 int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out,
                 uint64_t out_cap, uint32_t values_per_lane, uint64_t *total_out);
@@ -227,5 +229,7 @@ int enable(int on);
 } // namespace prof
 int analyze_table(const rngx_prof_event *events, uint32_t n, double elapsed_s,
                   rngx_prof_stats *out);
+// Write an event table as text or Chrome trace JSON (RNGX_EXPORT_*).
+int write_table(const rngx_prof_event *events, uint32_t n, const char *path, int format);
 
 } // namespace rngx

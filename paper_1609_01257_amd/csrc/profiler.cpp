@@ -9,6 +9,7 @@
 // (O(E log E + E*Q) for Q streams, instead of examining every pair), and
 // derives the effective time and the device/host split.
 #include <algorithm>
+#include <cerrno>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -452,5 +453,96 @@ int analyze_table(const rngx_prof_event *events, uint32_t n, double elapsed_s,
 }
 
 std::string summary_of(const rngx_prof_stats &st) { return format_summary(st); }
+
+namespace {
+
+// The event name with a terminating NUL; control characters become '_' so
+// a name can never break a line of the table.
+std::string clean_name(const char *raw)
+{
+    std::string s(raw, strnlen(raw, RNGX_PROF_NAME));
+    for (char &ch : s)
+        if ((unsigned char)ch < 0x20 || ch == 0x7f)
+            ch = '_';
+    return s;
+}
+
+void json_string(FILE *f, const std::string &s)
+{
+    std::fputc('"', f);
+    for (char ch : s) {
+        if (ch == '"' || ch == '\\')
+            std::fputc('\\', f);
+        std::fputc(ch, f);
+    }
+    std::fputc('"', f);
+}
+
+} // namespace
+
+int write_table(const rngx_prof_event *events, uint32_t n, const char *path, int format)
+{
+    if (!path)
+        return set_error(RNGX_E_INVAL, "profile export: NULL path");
+    if (n && !events)
+        return set_error(RNGX_E_INVAL, "profile export: NULL events with n > 0");
+    if (format != RNGX_EXPORT_TABLE && format != RNGX_EXPORT_TRACE)
+        return set_error(RNGX_E_INVAL, "profile export: unknown format %d", format);
+    for (uint32_t i = 0; i < n; ++i)
+        if (events[i].end_ns < events[i].start_ns)
+            return set_error(RNGX_E_INVAL, "profile export: event %u ends before it starts", i);
+    // Events by start time; queues numbered in order of their first event.
+    std::vector<uint32_t> order(n);
+    for (uint32_t i = 0; i < n; ++i)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return events[a].start_ns < events[b].start_ns;
+    });
+    std::vector<uint64_t> queues;
+    std::vector<uint32_t> qidx(n);
+    for (uint32_t i : order) {
+        uint32_t q = 0;
+        while (q < queues.size() && queues[q] != events[i].queue)
+            ++q;
+        if (q == queues.size())
+            queues.push_back(events[i].queue);
+        qidx[i] = q;
+    }
+    FILE *f = std::fopen(path, "w");
+    if (!f)
+        return set_error(RNGX_E_INVAL, "profile export: cannot open %s: %s", path,
+                         std::strerror(errno));
+    if (format == RNGX_EXPORT_TABLE) {
+        std::fprintf(f, "queue\tt_start\tt_end\tevent\n");
+        for (uint32_t i : order)
+            std::fprintf(f, "q%u\t%llu\t%llu\t%s\n", qidx[i],
+                         (unsigned long long)events[i].start_ns,
+                         (unsigned long long)events[i].end_ns,
+                         clean_name(events[i].name).c_str());
+    } else {
+        std::fprintf(f, "{\"displayTimeUnit\": \"ns\", \"traceEvents\": [");
+        bool first = true;
+        for (uint32_t q = 0; q < queues.size(); ++q) {
+            std::fprintf(f, "%s\n{\"name\": \"thread_name\", \"ph\": \"M\", \"pid\": 1, "
+                            "\"tid\": %u, \"args\": {\"name\": \"q%u\"}}",
+                         first ? "" : ",", q, q);
+            first = false;
+        }
+        for (uint32_t i : order) {
+            std::fprintf(f, "%s\n{\"name\": ", first ? "" : ",");
+            json_string(f, clean_name(events[i].name));
+            std::fprintf(f, ", \"cat\": \"rngx\", \"ph\": \"X\", \"pid\": 1, \"tid\": %u, "
+                            "\"ts\": %.3f, \"dur\": %.3f}",
+                         qidx[i], events[i].start_ns / 1e3,
+                         (events[i].end_ns - events[i].start_ns) / 1e3);
+            first = false;
+        }
+        std::fprintf(f, "\n]}\n");
+    }
+    const bool ok = !std::ferror(f);
+    if (std::fclose(f) != 0 || !ok)
+        return set_error(RNGX_E_INVAL, "profile export: cannot write %s", path);
+    return RNGX_OK;
+}
 
 } // namespace rngx

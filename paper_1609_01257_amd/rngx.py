@@ -22,6 +22,8 @@ RNGX_E_BUSY = -5
 RNGX_E_ABORTED = -6
 COPY_KERNEL = 0
 COPY_RUNTIME = 1
+EXPORT_TABLE = 0
+EXPORT_TRACE = 1
 
 CONSUME_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                               ctypes.c_size_t)
@@ -103,6 +105,8 @@ _SIGS = {
     "rngx_generate": ([_u32, _p, _p], _int),
     "rngx_generate_u32": ([_u32, _p, _p], _int),
     "rngx_info": ([_p, _p, _p], _int),
+    "rngx_get_state": ([_p, _u32, _p, _p], _int),
+    "rngx_set_state": ([_u64, _p, _u32, _u64], _int),
     "rngx_shutdown": ([], _int),
     "rngx_last_error": ([], ctypes.c_char_p),
     "rngx_strerror": ([_int], ctypes.c_char_p),
@@ -139,6 +143,8 @@ _SIGS = {
     "rngx_profile_stats": ([ctypes.POINTER(ProfStats)], _int),
     "rngx_profile_events": ([_p, _u32, ctypes.POINTER(_u32)], _int),
     "rngx_profile_analyze": ([_p, _u32, ctypes.c_double, ctypes.POINTER(ProfStats)], _int),
+    "rngx_profile_write": ([_p, _u32, ctypes.c_char_p, _int], _int),
+    "rngx_profile_export": ([ctypes.c_char_p, _int], _int),
 }
 
 
@@ -204,6 +210,23 @@ def info():
     s, n, c = _u64(), _u32(), _u64()
     _check(lib().rngx_info(ctypes.byref(s), ctypes.byref(n), ctypes.byref(c)))
     return s.value, n.value, c.value
+
+
+def get_state():
+    """Checkpoint: (states as a uint64 numpy array, seed, cursor)."""
+    import numpy as np
+    n = info()[1]
+    st = np.empty(n, dtype=np.uint64)
+    s, c = _u64(), _u64()
+    _check(lib().rngx_get_state(st.ctypes.data, n, ctypes.byref(s), ctypes.byref(c)))
+    return st, s.value, c.value
+
+
+def set_state(seed: int, states, cursor: int):
+    """Resume from a checkpoint taken by get_state (any process, any device)."""
+    import numpy as np
+    st = np.ascontiguousarray(states, dtype=np.uint64)
+    _check(lib().rngx_set_state(seed & (2**64 - 1), st.ctypes.data, len(st), cursor))
 
 
 def generate(n_iters: int, out, stream=None):
@@ -506,8 +529,7 @@ def profile_events() -> list:
             for i in range(n.value)]
 
 
-def profile_analyze(events, elapsed_s: float) -> dict:
-    """Analyse (name, queue, start_ns, end_ns) rows with the library's code."""
+def _event_array(events):
     arr = (ProfEvent * max(1, len(events)))()
     qid = {}
     for i, (name, q, s, e) in enumerate(events):
@@ -515,6 +537,22 @@ def profile_analyze(events, elapsed_s: float) -> dict:
         arr[i].queue = q if isinstance(q, int) else qid.setdefault(q, len(qid))
         arr[i].start_ns = s
         arr[i].end_ns = e
+    return arr
+
+
+def profile_write(events, path: str, fmt: int = EXPORT_TABLE):
+    """Write (name, queue, start_ns, end_ns) rows as a table or trace file."""
+    _check(lib().rngx_profile_write(_event_array(events), len(events), os.fsencode(path), fmt))
+
+
+def profile_export(path: str, fmt: int = EXPORT_TABLE):
+    """Write the current profiling window's events as a table or trace file."""
+    _check(lib().rngx_profile_export(os.fsencode(path), fmt))
+
+
+def profile_analyze(events, elapsed_s: float) -> dict:
+    """Analyse (name, queue, start_ns, end_ns) rows with the library's code."""
+    arr = _event_array(events)
     st = ProfStats()
     _check(lib().rngx_profile_analyze(arr, len(events), elapsed_s, ctypes.byref(st)))
     return _stats_dict(st)

@@ -51,6 +51,20 @@ def test_init_zero_states_is_inval():
     assert rngx.lib().rngx_init(0, 0) == rngx.RNGX_E_INVAL
 
 
+def test_checkpoint_argument_errors_without_gpu():
+    import numpy as np
+    L = rngx.lib()
+    rngx.shutdown()
+    buf = np.zeros(4, dtype=np.uint64)
+    assert L.rngx_get_state(buf.ctypes.data, 4, None, None) == rngx.RNGX_E_NOINIT
+    assert L.rngx_set_state(1, None, 4, 0) == rngx.RNGX_E_INVAL
+    ok = np.array([5, 6, 7, 8], dtype=np.uint64)
+    assert L.rngx_set_state(1, ok.ctypes.data, 0, 0) == rngx.RNGX_E_INVAL
+    bad = np.array([5, 6, 0, 8], dtype=np.uint64)          # xorshift fixes 0
+    assert L.rngx_set_state(1, bad.ctypes.data, 4, 0) == rngx.RNGX_E_INVAL
+    assert "state 2 is 0" in rngx.last_error()
+
+
 def test_set_launch_validation():
     for bad in [(32, 1, 0), (1088, 1, 0), (100, 1, 0), (256, 3, 0), (256, 0, 0), (256, 1, 2)]:
         cfg = rngx.Launch(*bad)
@@ -180,3 +194,51 @@ def test_server_pool_ring_and_ticket_table_model(tmp_path):
                     os.path.join(ROOT, "paper_1609_01257_amd", "csrc"), src, "-o", exe], check=True)
     r = subprocess.run([exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_profile_write_table_and_trace(tmp_path):
+    import json
+    ev = fig3_events()
+    rows = [(e.name, e.queue, e.start_ns, e.end_ns) for e in ev]
+    table = tmp_path / "events.tsv"
+    rngx.profile_write(rows, str(table), rngx.EXPORT_TABLE)
+    lines = table.read_text().splitlines()
+    assert lines[0].split("\t") == ["queue", "t_start", "t_end", "event"]
+    body = [l.split("\t") for l in lines[1:]]
+    assert len(body) == len(ev)
+    # Rows by start time; the first event's queue (Main) is q0, Comms is q1.
+    want = sorted(ev, key=lambda e: e.start_ns)
+    qname = {"Main": "q0", "Comms": "q1"}
+    assert body == [[qname[e.queue], str(e.start_ns), str(e.end_ns), e.name] for e in want]
+    trace = tmp_path / "events.json"
+    rngx.profile_write(rows, str(trace), rngx.EXPORT_TRACE)
+    doc = json.loads(trace.read_text())
+    meta = [x for x in doc["traceEvents"] if x["ph"] == "M"]
+    spans = [x for x in doc["traceEvents"] if x["ph"] == "X"]
+    assert sorted(m["args"]["name"] for m in meta) == ["q0", "q1"]
+    assert len(spans) == len(ev)
+    for x, e in zip(spans, want):
+        assert x["name"] == e.name and x["tid"] == int(qname[e.queue][1:])
+        assert x["ts"] == pytest.approx(e.start_ns / 1e3, abs=1e-3)
+        assert x["dur"] == pytest.approx((e.end_ns - e.start_ns) / 1e3, abs=1e-3)
+
+
+def test_profile_write_errors(tmp_path):
+    L = rngx.lib()
+    ok = rngx._event_array([("A", 0, 5, 9)])
+    assert L.rngx_profile_write(ok, 1, None, 0) == rngx.RNGX_E_INVAL
+    assert L.rngx_profile_write(None, 1, str(tmp_path / "x").encode(), 0) == rngx.RNGX_E_INVAL
+    assert L.rngx_profile_write(ok, 1, str(tmp_path / "x").encode(), 2) == rngx.RNGX_E_INVAL
+    back = rngx._event_array([("A", 0, 9, 5)])
+    assert L.rngx_profile_write(back, 1, str(tmp_path / "x").encode(), 0) == rngx.RNGX_E_INVAL
+    assert L.rngx_profile_write(ok, 1, str(tmp_path / "no" / "dir").encode(), 0) == rngx.RNGX_E_INVAL
+    assert "cannot open" in rngx.last_error()
+    # Names with quotes, backslashes or control characters stay well-formed.
+    import json
+    odd = rngx._event_array([('a"b\\c\td', 0, 1, 2)])
+    p = tmp_path / "odd.json"
+    assert L.rngx_profile_write(odd, 1, str(p).encode(), 1) == rngx.RNGX_OK
+    assert json.loads(p.read_text())["traceEvents"][-1]["name"] == 'a"b\\c_d'
+    p = tmp_path / "odd.tsv"
+    assert L.rngx_profile_write(odd, 1, str(p).encode(), 0) == rngx.RNGX_OK
+    assert p.read_text().splitlines()[1].split("\t") == ["q0", "1", "2", 'a"b\\c_d']

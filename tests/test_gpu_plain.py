@@ -217,3 +217,38 @@ def test_roofline_small_full(oracle):
     assert np.array_equal(got, oracle.generate(1, n, iters))
     got32 = run(1, n, iters, u32=True)
     assert np.array_equal(got32, oracle.generate_u32(1, n, iters))
+
+
+@pytest.mark.parametrize("n,i1,i2", [(1, 3, 5), (4099, 7, 11), (65536, 64, 1)])
+def test_checkpoint_resume_continues_the_streams(oracle, n, i1, i2):
+    seed = 0xfeedface12345678
+    rngx.init(seed, n)
+    first = torch.empty(n * i1, dtype=torch.int64, device="cuda")
+    rngx.generate(i1, first)
+    states, s, c = rngx.get_state()
+    assert (s, c) == (seed, i1)
+    # The checkpoint is the next value of every stream.
+    assert np.array_equal(states, oracle.generate(seed, n, 1, cursor=i1).ravel())
+    rngx.shutdown()
+    rngx.set_state(s, states, c)
+    assert rngx.info() == (seed, n, i1)
+    rest = torch.empty(n * i2, dtype=torch.int64, device="cuda")
+    rngx.generate(i2, rest)
+    torch.cuda.synchronize()
+    got = np.concatenate([_u64(first), _u64(rest)])
+    assert np.array_equal(got, oracle.generate(seed, n, i1 + i2).ravel())
+
+
+def test_set_state_from_oracle_states(oracle):
+    # States computed on the CPU (value number 1000 of each stream) resume the
+    # streams at that point, in u32 form too.
+    seed, n = 3, 333
+    rngx.set_state(seed, oracle.generate(seed, n, 1, cursor=1000).ravel(), 1000)
+    out = torch.empty(n * 4, dtype=torch.int32, device="cuda")
+    rngx.generate_u32(4, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u32(out), oracle.generate_u32(seed, n, 4, cursor=1000).ravel())
+    st, _, c = rngx.get_state()
+    assert c == 1004 and np.array_equal(st, oracle.generate(seed, n, 1, cursor=1004).ravel())
+    big = np.empty(n + 1, dtype=np.uint64)
+    assert rngx.lib().rngx_get_state(big.ctypes.data, n + 1, None, None) == rngx.RNGX_E_INVAL

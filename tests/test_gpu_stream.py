@@ -185,3 +185,29 @@ def test_paper_shaped_streaming_sampled(oracle, copy_mode):
     st = rngx.profile_stats()
     counts = {name: c for name, c, _, _ in st["agg"]}
     assert counts["READ_BUFFER"] == steps and counts["RNG_KERNEL"] == steps
+
+
+def test_profile_export_of_a_streamed_run(tmp_path):
+    # The exported table holds every logged event of the window: one init
+    # kernel, one generation kernel and one read per step, the reads on
+    # their own queue.
+    import json
+    n, steps = 1 << 16, 6
+    rngx.init(9, n)
+    dev0, dev1, host = _buffers(n, 1, 2)
+    rngx.stream_to_host(steps, 1, dev0, dev1, host, 2)
+    table = tmp_path / "t.tsv"
+    rngx.profile_export(str(table), rngx.EXPORT_TABLE)
+    rows = [l.split("\t") for l in table.read_text().splitlines()[1:]]
+    names = [r[3] for r in rows]
+    assert names.count("INIT_KERNEL") == 1 and names[0] == "INIT_KERNEL"
+    assert names.count("RNG_KERNEL") == steps and names.count("READ_BUFFER") == steps
+    assert {r[0] for r in rows if r[3] == "READ_BUFFER"}.isdisjoint(
+        {r[0] for r in rows if r[3] == "RNG_KERNEL"})
+    assert all(int(r[1]) <= int(r[2]) for r in rows)
+    starts = [int(r[1]) for r in rows]
+    assert starts == sorted(starts)
+    trace = tmp_path / "t.json"
+    rngx.profile_export(str(trace), rngx.EXPORT_TRACE)
+    spans = [x for x in json.loads(trace.read_text())["traceEvents"] if x["ph"] == "X"]
+    assert len(spans) == len(rows)
