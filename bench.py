@@ -203,12 +203,13 @@ def batched(torch, rngx, steps):
 
 def serving(torch, rngx, seconds, plain_gbs):
     """Serving: 2^20 resident streams, a 16 GB pool with memory-based
-    admission, Poisson arrivals at 2k / 10k / 50k req/s (stream id uniform,
+    admission, 4 streams, batches of up to 2,048 requests with at most 3 in
+    flight, Poisson arrivals at 2k / 10k / 50k req/s (stream id uniform,
     length log-uniform in [2^12, 2^22)), results released on completion;
     then a saturation run (a pre-filled backlog) for throughput."""
     from paper_1609_01257_amd import inputs
     pool = torch.empty(16 * 10**9, dtype=torch.uint8, device="cuda")
-    rngx.serve_start(1609, 1 << 20, pool, 4, 1024)
+    rngx.serve_start(1609, 1 << 20, pool, 4, 2048)
     res = {"workload": "2^20 resident streams, 16 GB pool, lengths floor(2^U[12,22)), "
                        "Poisson arrivals, %.0f s per rate" % seconds, "rates": []}
     try:
@@ -227,12 +228,17 @@ def serving(torch, rngx, seconds, plain_gbs):
                    "admission_stalls": st["admission_stalls"]}
             res["rates"].append(row)
             log("serving:", row)
-        # Saturation: a backlog of requests all arriving at once.
+        # Saturation: a backlog of requests all arriving at once, served three
+        # times (one run lasts ~50 ms and varies by a few per cent); the
+        # median run is reported.
         _, g, L = inputs.serving_arrivals(50000.0, 1.0, seed=4242)
         t = np.zeros(len(g))
-        st = rngx.serve_run_trace(t, g, L, timeout_s=600)
+        runs = sorted((rngx.serve_run_trace(t, g, L, timeout_s=600) for _ in range(3)),
+                      key=lambda r: r["gbs"])
+        st = runs[1]
         res["saturation"] = {"requests": st["completed"], "gb": round(st["bytes"] / 1e9, 2),
                              "gbs": round(st["gbs"], 1),
+                             "gbs_runs": [round(r["gbs"], 1) for r in runs],
                              "mean_batch": round(st["mean_batch_requests"], 1),
                              "admission_stalls": st["admission_stalls"],
                              "p99_us": round(st["lat_p99_us"], 1)}
@@ -302,6 +308,7 @@ def main():
         log("copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
         return
     if args.batched_only:
+        rngx.init(1, 64)          # opens the profiling window the step is timed in
         res = batched(torch, rngx, args.steps)
         log("batched:", res)
         rngx.shutdown()

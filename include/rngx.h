@@ -185,7 +185,7 @@ int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, int u32, void
  *   the page-locked host buffer through its device-mapped address (falls
  *   back to RNGX_COPY_RUNTIME if `host` is not page-locked memory);
  * RNGX_COPY_RUNTIME: hipMemcpyAsync on the copy stream.
- * blocks: workgroups of 256 lanes for the copy kernel (1..65536).
+ * blocks: workgroups of 256 lanes for the copy kernel (1..65536, default 16).
  * Errors: RNGX_E_INVAL for an unknown mode or blocks out of range. */
 #define RNGX_COPY_KERNEL 0
 #define RNGX_COPY_RUNTIME 1
@@ -227,7 +227,8 @@ int rngx_generate_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_
 /* Launch configuration of the batched kernel.
  * values_per_lane: S, values each lane produces per work item (16, 32, 64,
  *   128, 256, 512 or 1024); a work item is a tile of 64 * S output values.
- * waves_per_block: 1..4; blocks: 1..65536 (the persistent grid);
+ * waves_per_block: 1..4; blocks: 1..65536 (the persistent grid; 0 means 8
+ *   waves per compute unit);
  * use_graph: 1 to capture the table upload and the launch in a HIP graph
  *   once and replay it, 0 to launch directly;
  * row_values: values each lane stages in LDS per round before the wave
@@ -236,7 +237,10 @@ int rngx_generate_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_
  * run_items: 0..64, most work items a wave takes at once (0 means 1;
  *   fewer near the end of the batch, down to 1); within a run, a wave
  *   moving to the next tile of the same request carries each lane's state
- *   forward instead of jumping from the stream's start.
+ *   forward instead of jumping from the stream's start;
+ * per_item: 1 to launch one wave per work item instead (the grid is sized
+ *   to the items, there is no work counter, blocks and run_items are
+ *   ignored), 0 for the persistent grid.
  * The output never depends on the configuration. */
 typedef struct rngx_batch_cfg {
     uint32_t values_per_lane;
@@ -245,6 +249,7 @@ typedef struct rngx_batch_cfg {
     uint32_t use_graph;
     uint32_t row_values;
     uint32_t run_items;
+    uint32_t per_item;
 } rngx_batch_cfg;
 
 int rngx_set_batch_cfg(const rngx_batch_cfg *cfg);
@@ -265,8 +270,10 @@ typedef struct rngx_tune_result {
 } rngx_tune_result;
 
 /* Autotuner (the paper's work-size suggestion, Section 6.1, made empirical):
- * time every candidate launch configuration (values_per_lane x
- * waves_per_block x waves per compute unit x row_values) on this request table with HIP events, check
+ * time every candidate launch configuration (values_per_lane 64..512 x
+ * waves_per_block x [persistent: run_items 1 or 8 x waves per compute unit,
+ * those whose LDS fits | one wave per item], 16-value rows) on this
+ * request table with HIP events, check
  * that every candidate's output has the same checksum, keep the fastest as
  * the batch configuration, and report all of them. `out` receives the
  * requests' output. reps: timed launches per candidate (>= 1).
@@ -377,6 +384,13 @@ int rngx_serve_run_trace(const double *arrival_s, const uint32_t *stream_id,
  * returns RNGX_E_BUSY beyond it (default 2^20; kept across restarts).
  * Errors: RNGX_E_INVAL if max_pending == 0. */
 int rngx_serve_set_max_pending(uint64_t max_pending);
+
+/* Bound on batches in flight (launched and not yet complete; default 3, kept
+ * across restarts). While that many run, newly admitted requests wait and
+ * join the next batch: under load batches grow instead of many small ones
+ * competing on the device, and batches stay queued behind the running one.
+ * Errors: RNGX_E_INVAL unless 1 <= max_inflight <= 32. */
+int rngx_serve_set_max_inflight(uint32_t max_inflight);
 
 /* Stop the server: requests not yet launched are dropped, launched batches
  * are waited for, resident states and streams are freed (the pool is the

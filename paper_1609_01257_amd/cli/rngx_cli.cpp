@@ -90,6 +90,9 @@ int main(int argc, char **argv)
     if (k > iters && iters > 0)
         k = iters;
     const size_t esize = u32 ? 4 : 8;
+    // Two device buffers and `slots` host slots of one step each.
+    if (k > (1ull << 40) / (n * esize) / slots)
+        return usage("a step of k iterations times host slots exceeds 1 TiB");
     const size_t step_bytes = (size_t)k * n * esize;
 
     int rc = rngx_init(seed, (uint32_t)n);

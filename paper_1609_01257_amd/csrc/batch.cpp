@@ -41,7 +41,7 @@ struct BatchGlobals {
     uint64_t *d_carry_nib = nullptr; // T^(63 S) nibble tables for each allowed S (kNumS x 256)
     uint64_t *d_acc = nullptr;    // checksum accumulator
     uint64_t *h_acc = nullptr;    // page-locked copy of it
-    rngx_batch_cfg cfg{256, 4, 0, 1, 16, 1};
+    rngx_batch_cfg cfg{256, 4, 0, 1, 16, 1, 0};
     BatchSlot api_slot;
 };
 
@@ -139,8 +139,8 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int 
 rngx_batch_cfg resolved_cfg(const rngx_batch_cfg &c, int n_cus)
 {
     rngx_batch_cfg r = c;
-    if (r.blocks == 0) // 16 waves per compute unit
-        r.blocks = (uint32_t)std::max(1, n_cus * 16 / (int)r.waves_per_block);
+    if (r.blocks == 0) // 8 waves per compute unit: the autotuner's usual pick
+        r.blocks = (uint32_t)std::max(1, n_cus * 8 / (int)r.waves_per_block);
     return r;
 }
 
@@ -267,7 +267,15 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
     if (rc)
         return rc;
     rngx_batch_cfg cfg = resolved_cfg(cfg_in, n_cus);
-    if (fit_grid && !cfg.use_graph) {
+    if (cfg.per_item) {
+        // One wave per item: the grid follows the item count (a captured
+        // graph is re-captured when that count changes).
+        const uint64_t need = (slot.n_items + cfg.waves_per_block - 1) / cfg.waves_per_block;
+        if (need > 0x7fffffffull)
+            return set_error(RNGX_E_INVAL, "batch: %llu work items exceed one grid",
+                             (unsigned long long)slot.n_items);
+        cfg.blocks = (uint32_t)std::max<uint64_t>(1, need);
+    } else if (fit_grid && !cfg.use_graph) {
         const uint64_t need = (slot.n_items + cfg.waves_per_block - 1) / cfg.waves_per_block;
         if (need < cfg.blocks)
             cfg.blocks = (uint32_t)std::max<uint64_t>(1, need);
@@ -283,7 +291,8 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
                           slot.exec_cfg.waves_per_block == cfg.waves_per_block &&
                           slot.exec_cfg.blocks == cfg.blocks &&
                           slot.exec_cfg.row_values == cfg.row_values &&
-                          slot.exec_cfg.run_items == cfg.run_items;
+                          slot.exec_cfg.run_items == cfg.run_items &&
+                          slot.exec_cfg.per_item == cfg.per_item;
         if (!same) {
             if (slot.exec) {
                 (void)hipGraphExecDestroy(slot.exec);
@@ -454,27 +463,34 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
     uint64_t ref_sum = 0, total = 0;
     bool have_ref = false;
     double best = 1e300;
-    // values_per_lane x waves_per_block x waves per compute unit x row length;
-    // combinations whose LDS would not fit the waves per CU are skipped.
-    const uint32_t svals[4] = {128, 256, 512, 1024};
+    // values_per_lane x run length x waves_per_block x waves per compute
+    // unit, all with 128-byte rows (64-byte rows write half cache lines and
+    // were much slower in every measurement); combinations whose LDS would
+    // not fit the waves per CU are skipped.
+    const uint32_t svals[4] = {64, 128, 256, 512};
+    const uint32_t runs[2] = {1, 8};
     const uint32_t wpbs[2] = {2, 4};
     const uint32_t waves_per_cu[3] = {8, 16, 32};
-    const uint32_t rows[2] = {8, 16};
+    const uint32_t row = 16;
+    // Persistent candidates, then one wave per item (runs and waves per CU
+    // do not apply there: ui = 2 marks those, once per S and block size).
     for (uint32_t si = 0; si < 4; ++si) {
+      for (uint32_t ui = 0; ui < 3; ++ui) {
         for (uint32_t wi = 0; wi < 2; ++wi) {
             for (uint32_t oi = 0; oi < 3; ++oi) {
-              for (uint32_t ri = 0; ri < 2; ++ri) {
-                const uint32_t lds_per_block =
-                    8u * (kCarryTable + wpbs[wi] * 64u * (rows[ri] + 2));
-                if (waves_per_cu[oi] / wpbs[wi] * lds_per_block > 160u * 1024u)
+                const bool per_item = ui == 2;
+                const uint32_t lds_per_block = 8u * (kCarryTable + wpbs[wi] * 64u * (row + 2));
+                if (per_item ? oi > 0
+                             : waves_per_cu[oi] / wpbs[wi] * lds_per_block > 160u * 1024u)
                     continue;
                 rngx_batch_cfg c;
                 c.values_per_lane = svals[si];
                 c.waves_per_block = wpbs[wi];
                 c.blocks = (uint32_t)std::max(1, n_cus * (int)waves_per_cu[oi] / (int)wpbs[wi]);
                 c.use_graph = g.cfg.use_graph;
-                c.row_values = rows[ri];
-                c.run_items = g.cfg.run_items;
+                c.row_values = row;
+                c.run_items = per_item ? 1 : runs[ui];
+                c.per_item = per_item ? 1 : 0;
                 rc = batch_stage(g.api_slot, reqs, m, out, out_cap, c.values_per_lane, &total);
                 if (rc)
                     return rc;
@@ -516,9 +532,9 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
                     best = mean;
                     result->best = c;
                 }
-              }
             }
         }
+      }
     }
     result->best_ms = best;
     result->best_gbs = (double)total * 8.0 / (best * 1e-3) / 1e9;

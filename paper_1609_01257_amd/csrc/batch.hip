@@ -97,24 +97,28 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
                                                     const uint64_t *__restrict__ pow2,
                                                     const uint64_t *__restrict__ rows_s,
                                                     const uint64_t *__restrict__ carry_nib,
-                                                    uint32_t run_items)
+                                                    uint32_t run_items, uint32_t per_item)
 {
     constexpr uint64_t C = 64ull * S;
     constexpr int ROUND = R;
     constexpr int LDS_ROW = lds_row(R);
     constexpr uint32_t CPR = R / 2;     // 16-byte chunks per row
     constexpr uint32_t RPI = 64 / CPR;  // rows per store instruction
-    // Dynamic LDS: the carry table, then 64 * LDS_ROW u64 per wave.
+    // Dynamic LDS: 64 * LDS_ROW u64 per wave, then the carry table (rows
+    // first keeps row addresses small enough for the LDS offset fields).
     extern __shared__ uint64_t lds_dyn[];
     const uint32_t lane = threadIdx.x & 63u;
     // Wave index, made provably uniform so item bookkeeping runs on the
     // scalar unit and the request table is read with scalar loads.
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint64_t *carry_tab = lds_dyn;
-    uint64_t *lds = lds_dyn + kCarryTable + (size_t)wid * 64 * LDS_ROW;
-    for (uint32_t i = threadIdx.x; i < (uint32_t)kCarryTable; i += blockDim.x)
-        carry_tab[i] = carry_nib[i];
-    __syncthreads();
+    uint64_t *carry_tab = lds_dyn + (size_t)(blockDim.x >> 6) * 64 * LDS_ROW;
+    uint64_t *lds = lds_dyn + (size_t)wid * 64 * LDS_ROW;
+    if (!per_item) {
+        // Only runs carry state; the barrier is uniform (per_item is).
+        for (uint32_t i = threadIdx.x; i < (uint32_t)kCarryTable; i += blockDim.x)
+            carry_tab[i] = carry_nib[i];
+        __syncthreads();
+    }
 
     const uint64_t n_items = desc->n_items;
     const uint32_t m = desc->m;
@@ -136,8 +140,17 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
     uint32_t lo = 0;
     bool carry = false;
     uint64_t x = 0;
+    if (per_item) {
+        // One wave per work item: the grid covers the items exactly once.
+        item = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wid;
+        if (item >= n_items)
+            return;
+        run_end = item + 1;
+    }
     for (;;) {
         if (item >= run_end) {
+            if (per_item)
+                break;
             uint64_t want = 1;
             if (run_items > 1) {
                 const uint64_t share = (n_items > seen ? n_items - seen : 0) / (2 * n_waves);
@@ -235,11 +248,14 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
                     const uint32_t row = RPI * i + lane / CPR;
                     v[i] = *reinterpret_cast<const u64x2 *>(&lds[row * LDS_ROW + 2u * ch]);
                 }
+                // Wave-uniform tile base plus a 32-bit lane offset (a tile
+                // is at most 512 KiB).
+                g_u64 *__restrict__ tile = obase + T0;
 #pragma unroll
                 for (uint32_t i = 0; i < CPR; ++i) {
                     const uint32_t row = RPI * i + lane / CPR;
-                    const uint64_t P = T0 + (uint64_t)row * S + (uint64_t)rd * ROUND + 2u * ch;
-                    *(g_u64x2 *)(obase + P) = v[i];
+                    const uint32_t off = row * (uint32_t)S + rd * (uint32_t)ROUND + 2u * ch;
+                    *(g_u64x2 *)(tile + off) = v[i];
                 }
             } else {
 #pragma unroll
@@ -276,10 +292,10 @@ hipError_t launch_batch_s(const BatchDesc *desc, const BatchTables &t, const rng
     const uint32_t run = c.run_items ? c.run_items : 1;
     if (c.row_values == 8)
         batch_kernel<S, 8><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
-            desc, t.pow2, t.rows_s, t.carry_nib, run);
+            desc, t.pow2, t.rows_s, t.carry_nib, run, c.per_item);
     else
         batch_kernel<S, 16><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
-            desc, t.pow2, t.rows_s, t.carry_nib, run);
+            desc, t.pow2, t.rows_s, t.carry_nib, run, c.per_item);
     return hipGetLastError();
 }
 
@@ -318,7 +334,7 @@ bool batch_cfg_valid(const rngx_batch_cfg &c)
                       c.values_per_lane == 1024;
     return s_ok && c.waves_per_block >= 1 && c.waves_per_block <= MAX_WAVES_PER_BLOCK &&
            c.blocks <= 65536 && c.use_graph <= 1 && (c.row_values == 8 || c.row_values == 16) &&
-           c.run_items <= 64;
+           c.run_items <= 64 && c.per_item <= 1;
 }
 
 hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const BatchTables &t,

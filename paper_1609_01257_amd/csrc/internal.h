@@ -202,7 +202,9 @@ struct Generator {
     hipEvent_t gen_done[2] = {nullptr, nullptr};
     hipEvent_t copy_done[2] = {nullptr, nullptr};
     int copy_mode = RNGX_COPY_KERNEL;
-    uint32_t copy_blocks = 128; // 32+ already saturate PCIe 5.0 x16 on MI355X
+    // 16 workgroups saturate PCIe 5.0 x16 on MI355X and slow the overlapping
+    // generation kernel least (measured: 16 to 256 all within 4 %).
+    uint32_t copy_blocks = 16;
 };
 
 Generator &generator();

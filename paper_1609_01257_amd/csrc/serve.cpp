@@ -94,7 +94,8 @@ struct Server {
     std::vector<hipStream_t> streams;
     uint32_t max_batch = 1024;
     uint64_t max_pending = 1u << 20;
-    rngx_batch_cfg cfg{256, 4, 0, 0, 16, 1};
+    uint32_t max_inflight = 3;
+    rngx_batch_cfg cfg{256, 4, 0, 0, 16, 1, 0};
     std::thread worker;
     int worker_rc = RNGX_OK;
     std::string worker_msg;
@@ -254,6 +255,11 @@ void worker_main(Server *sp)
         if (!s.stopping)
             progress |= admit(s);
         while (!s.stopping && !s.admitted.empty()) {
+            uint32_t inflight = 0;
+            for (const Flight &f : s.flights)
+                inflight += f.busy;
+            if (inflight >= s.max_inflight)
+                break;
             // An idle slot on the stream with the fewest batches in flight.
             Flight *idle = nullptr;
             uint32_t best = ~0u;
@@ -713,9 +719,11 @@ extern "C" int rngx_serve_run_trace(const double *arrival_s, const uint32_t *str
             __builtin_ia32_pause();
             t = now_ns();
         }
-        // Every request whose arrival time has passed goes in one submission.
+        // Every request whose arrival time has passed is submitted now, in
+        // chunks of at most 512 so that the scheduler can start launching
+        // while a large backlog is still being submitted.
         uint64_t j = i + 1;
-        while (j < k && t0 + (uint64_t)(arrival_s[j] * 1e9) <= t)
+        while (j < k && j - i < 512 && t0 + (uint64_t)(arrival_s[j] * 1e9) <= t)
             ++j;
         const int rc = submit_many_impl(stream_id + i, length + i, j - i, RNGX_SERVE_AUTORELEASE,
                                         nullptr);
@@ -747,6 +755,18 @@ extern "C" int rngx_serve_set_max_pending(uint64_t max_pending)
         return set_error(RNGX_E_INVAL, "serve: max_pending must be >= 1");
     s.max_pending = max_pending;
     s.cv_done.notify_all();
+    return RNGX_OK;
+}
+
+extern "C" int rngx_serve_set_max_inflight(uint32_t max_inflight)
+{
+    Server &s = SV();
+    std::lock_guard<std::mutex> lk(s.mu);
+    clear_error();
+    if (max_inflight == 0 || max_inflight > 32)
+        return set_error(RNGX_E_INVAL, "serve: max_inflight must be in 1..32");
+    s.max_inflight = max_inflight;
+    s.cv_work.notify_all();
     return RNGX_OK;
 }
 

@@ -42,7 +42,8 @@ class RngxError(RuntimeError):
 class BatchCfg(ctypes.Structure):
     _fields_ = [("values_per_lane", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
                 ("blocks", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
-                ("row_values", ctypes.c_uint32), ("run_items", ctypes.c_uint32)]
+                ("row_values", ctypes.c_uint32), ("run_items", ctypes.c_uint32),
+                ("per_item", ctypes.c_uint32)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -135,6 +136,7 @@ _SIGS = {
     "rngx_serve_run_trace": ([_p, _p, _p, _u64, ctypes.c_double, ctypes.POINTER(ServeReport)],
                              _int),
     "rngx_serve_set_max_pending": ([_u64], _int),
+    "rngx_serve_set_max_inflight": ([_u32], _int),
     "rngx_serve_stop": ([], _int),
     "rngx_profile_start": ([], _int),
     "rngx_profile_stop": ([], _int),
@@ -328,9 +330,9 @@ def generate_batch(reqs, out, stream=None):
 
 
 def set_batch_cfg(values_per_lane=256, waves_per_block=4, blocks=0, use_graph=True,
-                  row_values=16, run_items=1):
+                  row_values=16, run_items=1, per_item=False):
     cfg = BatchCfg(values_per_lane, waves_per_block, blocks, int(bool(use_graph)), row_values,
-                   run_items)
+                   run_items, int(bool(per_item)))
     _check(lib().rngx_set_batch_cfg(ctypes.byref(cfg)))
 
 
@@ -343,7 +345,7 @@ def get_batch_cfg():
 def _cfg_dict(c):
     return {"values_per_lane": c.values_per_lane, "waves_per_block": c.waves_per_block,
             "blocks": c.blocks, "use_graph": bool(c.use_graph), "row_values": c.row_values,
-            "run_items": c.run_items}
+            "run_items": c.run_items, "per_item": bool(c.per_item)}
 
 
 def autotune_batch(reqs, out, reps=2, stream=None):
@@ -456,6 +458,10 @@ def serve_run_trace(arrival_s, stream_id, length, timeout_s: float = 600.0) -> d
     _check(lib().rngx_serve_run_trace(a.ctypes.data, g.ctypes.data, n.ctypes.data, len(a),
                                       timeout_s, ctypes.byref(r)))
     return _report(r)
+
+
+def serve_set_max_inflight(max_inflight: int):
+    _check(lib().rngx_serve_set_max_inflight(max_inflight))
 
 
 def serve_set_max_pending(n: int):

@@ -161,12 +161,16 @@ def test_batch_argument_errors_without_gpu():
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, None, 3, None) == rngx.RNGX_E_INVAL
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, None, 4, None) == rngx.RNGX_E_INVAL
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, 8, 4, None) == rngx.RNGX_E_INVAL  # misaligned
-    for bad in [(100, 4, 0, 1, 16, 1), (256, 5, 0, 1, 16, 1), (256, 4, 70000, 1, 16, 1),
-                (256, 4, 0, 2, 16, 1), (256, 4, 0, 1, 12, 1), (256, 4, 0, 1, 16, 65)]:
+    for bad in [(100, 4, 0, 1, 16, 1, 0), (256, 5, 0, 1, 16, 1, 0), (256, 4, 70000, 1, 16, 1, 0),
+                (256, 4, 0, 2, 16, 1, 0), (256, 4, 0, 1, 12, 1, 0), (256, 4, 0, 1, 16, 65, 0),
+                (256, 4, 0, 1, 16, 1, 2)]:
         assert L.rngx_set_batch_cfg(ctypes.byref(rngx.BatchCfg(*bad))) == rngx.RNGX_E_INVAL, bad
     rngx.set_batch_cfg(512, 2, 100, False, 8, 3)
     assert rngx.get_batch_cfg() == {"values_per_lane": 512, "waves_per_block": 2, "blocks": 100,
-                                    "use_graph": False, "row_values": 8, "run_items": 3}
+                                    "use_graph": False, "row_values": 8, "run_items": 3,
+                                    "per_item": False}
+    rngx.set_batch_cfg(64, 4, 0, True, 16, 1, True)
+    assert rngx.get_batch_cfg()["per_item"] is True
     rngx.set_batch_cfg()
 
 
@@ -182,6 +186,14 @@ def test_serve_calls_before_start_are_noinit():
     assert L.rngx_serve_start(1, 0, 4096, 1 << 16, 4, 16) == rngx.RNGX_E_INVAL
     assert L.rngx_serve_start(1, 10, 4096 + 8, 1 << 16, 4, 16) == rngx.RNGX_E_INVAL
     assert L.rngx_serve_set_max_pending(0) == rngx.RNGX_E_INVAL
+
+
+def test_serve_max_inflight_validation():
+    L = rngx.lib()
+    assert L.rngx_serve_set_max_inflight(0) == rngx.RNGX_E_INVAL
+    assert L.rngx_serve_set_max_inflight(33) == rngx.RNGX_E_INVAL
+    assert L.rngx_serve_set_max_inflight(32) == rngx.RNGX_OK
+    assert L.rngx_serve_set_max_inflight(3) == rngx.RNGX_OK
 
 
 def test_server_pool_ring_and_ticket_table_model(tmp_path):

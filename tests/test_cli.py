@@ -19,7 +19,9 @@ def _run(*args, timeout=120):
 
 @pytest.mark.parametrize("args", [(), ("5",), ("0", "3"), ("5", "-1"), ("x", "3"),
                                   ("5", "3", "7"), ("-k", "0", "5", "3"), ("-s",),
-                                  ("4294967296", "1"), ("-h", "0", "5", "3")])
+                                  ("4294967296", "1"), ("-h", "0", "5", "3"),
+                                  ("-k", "4294967295", "-h", "4294967295", "4294967295",
+                                   "4294967295")])
 def test_usage_errors(args):
     r = _run(*args)
     assert r.returncode == 2 and b"usage:" in r.stderr and r.stdout == b""

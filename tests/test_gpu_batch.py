@@ -44,12 +44,32 @@ def test_small_ragged_tables(oracle, seed):
 
 
 @pytest.mark.parametrize("S,wpb,graph,row,run", list(itertools.product(
-    [16, 32, 64, 128, 256, 512, 1024], [1, 2, 4], [False, True], [8, 16], [1, 3, 8])))
+    [16, 32, 64, 128, 256, 512, 1024], [1, 2, 4], [False, True], [8, 16], [1, 3, 8, 64])))
 def test_every_launch_config(oracle, S, wpb, graph, row, run):
     r = inputs.ragged_requests(m=23, seed=99, max_len=400000, max_offset=5000)
     exp = oracle.generate_batch(_oracle_reqs(oracle, r))
     rngx.set_batch_cfg(S, wpb, 37, graph, row, run)
     assert np.array_equal(_run(_reqs(r), r.total), exp)
+
+
+@pytest.mark.parametrize("S,wpb,graph,row", list(itertools.product(
+    [16, 32, 64, 128, 256, 512, 1024], [1, 2, 4], [False, True], [8, 16])))
+def test_every_per_item_config(oracle, S, wpb, graph, row):
+    # One wave per work item: the grid follows the item count.
+    r = inputs.ragged_requests(m=23, seed=98, max_len=400000, max_offset=5000)
+    exp = oracle.generate_batch(_oracle_reqs(oracle, r))
+    rngx.set_batch_cfg(S, wpb, 0, graph, row, 1, True)
+    assert np.array_equal(_run(_reqs(r), r.total), exp)
+
+
+def test_per_item_graph_follows_item_count(oracle):
+    # The captured graph is re-captured when the item count changes and
+    # reused when it does not; every replay checked against the oracle.
+    rngx.set_batch_cfg(64, 4, 0, True, 16, 1, True)
+    for k, (m, seed) in enumerate([(40, 1), (41, 2), (41, 2), (7, 3), (40, 1)]):
+        r = inputs.ragged_requests(m=m, seed=2000 + seed, max_len=50000, max_offset=10**6)
+        exp = oracle.generate_batch(_oracle_reqs(oracle, r))
+        assert np.array_equal(_run(_reqs(r), r.total), exp), k
 
 
 def test_tiny_and_zero_length_requests(oracle):
@@ -59,8 +79,9 @@ def test_tiny_and_zero_length_requests(oracle):
                         np.arange(m, dtype=np.uint32) * 1000,
                         np.arange(m, dtype=np.uint64) * 7, np.array(lengths, dtype=np.uint64))
     exp = oracle.generate_batch(_oracle_reqs(oracle, r))
-    for graph, row, run in ((False, 16, 1), (True, 8, 4)):
-        rngx.set_batch_cfg(64, 1, 5, graph, row, run)
+    for graph, row, run, per_item in ((False, 16, 1, False), (True, 8, 4, False),
+                                      (False, 16, 1, True), (True, 8, 1, True)):
+        rngx.set_batch_cfg(64, 1, 5, graph, row, run, per_item)
         assert np.array_equal(_run(_reqs(r), r.total), exp)
 
 
@@ -128,7 +149,9 @@ def test_autotune_agrees_across_candidates(oracle):
     r = inputs.ragged_requests(m=64, seed=8, max_len=300000)
     out = torch.zeros(r.total, dtype=torch.int64, device="cuda")
     res = rngx.autotune_batch(_reqs(r), out, reps=1)
-    assert len(res["tried"]) >= 40 and res["best_ms"] > 0
+    assert len(res["tried"]) >= 32 and res["best_ms"] > 0
+    assert {c["run_items"] for c, _ in res["tried"]} == {1, 8}
+    assert {c["per_item"] for c, _ in res["tried"]} == {False, True}
     assert rngx.get_batch_cfg() == res["best"]
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint64),
@@ -162,6 +185,11 @@ def test_batched_config_full_size_sampled(oracle):
         got = out[int(starts[j]):int(starts[j + 1])].cpu().numpy().view(np.uint64)
         one = oracle.make_reqs([r.seeds[j]], [r.gids[j]], [0], [r.lengths[j]])
         assert np.array_equal(got, oracle.generate_batch(one)), j
+    rngx.generate_batch(_reqs(r), out)
+    assert rngx.checksum(out, r.total) == c1
+    # The same table with one wave per item: same output.
+    rngx.set_batch_cfg(64, 4, 0, True, 16, 1, True)
+    out.zero_()
     rngx.generate_batch(_reqs(r), out)
     assert rngx.checksum(out, r.total) == c1
     del out

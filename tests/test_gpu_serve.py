@@ -25,6 +25,7 @@ def server():
     yield start
     rngx.serve_stop()
     rngx.serve_set_max_pending(1 << 20)
+    rngx.serve_set_max_inflight(3)
     pools.clear()
     torch.cuda.empty_cache()
 
@@ -194,3 +195,20 @@ def test_serving_shape_sampled(oracle, server):
         got = _values(pool, rngx.serve_wait(tk, 60.0), b)
         rngx.serve_release(tk)
         assert np.array_equal(got, e), (a, b)
+
+
+@pytest.mark.parametrize("max_inflight", [1, 3, 8])
+def test_inflight_cap_keeps_results(oracle, server, max_inflight):
+    # A backlog served with different caps on batches in flight: batching
+    # changes, results do not.
+    seed, n_states = 4242, 200
+    rngx.serve_set_max_inflight(max_inflight)
+    pool = server(seed, n_states, 256 << 20, 4, 32)
+    hist = _history(max_inflight, 300, n_states, 30000)
+    tickets = rngx.serve_submit_many([g for g, _ in hist], [L for _, L in hist])
+    exp = oracle.serve_expected(seed, hist)
+    for t, (g, L), e in zip(tickets, hist, exp):
+        assert np.array_equal(_values(pool, rngx.serve_wait(int(t), 60.0), L), e)
+        rngx.serve_release(int(t))
+    st = rngx.serve_stats()
+    assert st["completed"] == len(hist) and st["batches"] >= len(hist) // 32
