@@ -37,7 +37,7 @@ struct BatchGlobals {
     int device = -1;
     int n_cus = 0;
     uint64_t *d_pow2 = nullptr;   // 64 matrices x 64 rows
-    uint64_t *d_rows_s = nullptr;     // T^S rows for each allowed S (kNumS x 64)
+    uint64_t *d_spread = nullptr;     // lane-spread tables for each allowed S (kNumS x kSpreadTable)
     uint64_t *d_carry_nib = nullptr; // T^(63 S) nibble tables for each allowed S (kNumS x 256)
     uint64_t *d_acc = nullptr;    // checksum accumulator
     uint64_t *h_acc = nullptr;    // page-locked copy of it
@@ -70,7 +70,7 @@ void free_slot(BatchSlot &s)
 
 } // namespace
 
-int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus,
+int batch_tables_locked(const uint64_t **pow2, const uint64_t **spread_all, int *n_cus,
                         const uint64_t **carry_nib_all)
 {
     // Own lock: the server thread reaches here without the batch API lock.
@@ -82,24 +82,44 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int 
     if (g.device != dev || !g.d_pow2) {
         if (g.d_pow2)
             (void)hipFree(g.d_pow2);
-        if (g.d_rows_s)
-            (void)hipFree(g.d_rows_s);
+        if (g.d_spread)
+            (void)hipFree(g.d_spread);
         if (g.d_carry_nib)
             (void)hipFree(g.d_carry_nib);
         if (g.d_acc)
             (void)hipFree(g.d_acc);
         if (g.h_acc)
             (void)hipHostFree(g.h_acc);
-        g.d_pow2 = g.d_rows_s = g.d_carry_nib = g.d_acc = g.h_acc = nullptr;
-        std::vector<uint64_t> rows(kNumS * 64), nib(kNumS * kCarryTable, 0);
+        g.d_pow2 = g.d_spread = g.d_carry_nib = g.d_acc = g.h_acc = nullptr;
+        std::vector<uint64_t> spread((size_t)kNumS * kSpreadTable, 0),
+            nib(kNumS * kCarryTable, 0);
         for (int i = 0; i < kNumS; ++i) {
-            power_rows(kValuesPerLane[i], rows.data() + 64 * i);
+            const uint64_t S = kValuesPerLane[i];
+            // Lane spread: entry ((16 q + v) * 64 + m) is T^(m S) (v << 4q),
+            // so a lane m places above a wave-uniform state z with the XOR of
+            // one entry per nibble of z.
+            uint64_t *sp = spread.data() + (size_t)kSpreadTable * i;
+            for (uint32_t m = 0; m < 64; ++m) {
+                uint64_t rows[64], col[64] = {0};
+                power_rows(m * S, rows);
+                for (int r = 0; r < 64; ++r)
+                    for (int j = 0; j < 64; ++j)
+                        col[j] |= ((rows[r] >> j) & 1u) << r;
+                for (int q = 0; q < 16; ++q)
+                    for (int v = 0; v < 16; ++v) {
+                        uint64_t e = 0;
+                        for (int b = 0; b < 4; ++b)
+                            if ((v >> b) & 1)
+                                e ^= col[4 * q + b];
+                        sp[(16 * q + v) * 64 + m] = e;
+                    }
+            }
             // A lane that just emitted its S values of a tile is C - S = 63 S
             // values short of its start in the next tile. M = T^(63 S) is
             // stored as 16 tables of 16 entries: entry v of table q is
             // M (v << 4q), so M x is the XOR of 16 lookups, one per nibble.
             uint64_t carry_rows[64];
-            power_rows(63ull * kValuesPerLane[i], carry_rows);
+            power_rows(63ull * S, carry_rows);
             uint64_t col[64] = {0};
             for (int r = 0; r < 64; ++r)
                 for (int j = 0; j < 64; ++j)
@@ -112,13 +132,13 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int 
                             t[16 * q + v] ^= col[4 * q + b];
         }
         RNGX_HIP(hipMalloc(&g.d_pow2, 64 * 64 * sizeof(uint64_t)));
-        RNGX_HIP(hipMalloc(&g.d_rows_s, rows.size() * sizeof(uint64_t)));
+        RNGX_HIP(hipMalloc(&g.d_spread, spread.size() * sizeof(uint64_t)));
         RNGX_HIP(hipMalloc(&g.d_carry_nib, nib.size() * sizeof(uint64_t)));
         RNGX_HIP(hipMalloc(&g.d_acc, sizeof(uint64_t)));
         RNGX_HIP(hipHostMalloc(&g.h_acc, sizeof(uint64_t), hipHostMallocDefault));
         RNGX_HIP(hipMemcpy(g.d_pow2, jump_tables(), 64 * 64 * sizeof(uint64_t),
                            hipMemcpyHostToDevice));
-        RNGX_HIP(hipMemcpy(g.d_rows_s, rows.data(), rows.size() * sizeof(uint64_t),
+        RNGX_HIP(hipMemcpy(g.d_spread, spread.data(), spread.size() * sizeof(uint64_t),
                            hipMemcpyHostToDevice));
         RNGX_HIP(hipMemcpy(g.d_carry_nib, nib.data(), nib.size() * sizeof(uint64_t),
                            hipMemcpyHostToDevice));
@@ -127,8 +147,8 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int 
     }
     if (pow2)
         *pow2 = g.d_pow2;
-    if (rows_s_all)
-        *rows_s_all = g.d_rows_s;
+    if (spread_all)
+        *spread_all = g.d_spread;
     if (carry_nib_all)
         *carry_nib_all = g.d_carry_nib;
     if (n_cus)
@@ -261,9 +281,9 @@ int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out
 int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stream,
                  bool fit_grid, const char *prof_name)
 {
-    const uint64_t *pow2 = nullptr, *rows_all = nullptr, *nib_all = nullptr;
+    const uint64_t *pow2 = nullptr, *spread_all = nullptr, *nib_all = nullptr;
     int n_cus = 0;
-    int rc = batch_tables_locked(&pow2, &rows_all, &n_cus, &nib_all);
+    int rc = batch_tables_locked(&pow2, &spread_all, &n_cus, &nib_all);
     if (rc)
         return rc;
     rngx_batch_cfg cfg = resolved_cfg(cfg_in, n_cus);
@@ -282,7 +302,7 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
     }
     BatchTables tabs;
     tabs.pow2 = pow2;
-    tabs.rows_s = rows_all + 64 * s_index(cfg.values_per_lane);
+    tabs.spread = spread_all + (size_t)kSpreadTable * s_index(cfg.values_per_lane);
     tabs.carry_nib = nib_all + kCarryTable * s_index(cfg.values_per_lane);
     const BatchDesc *ddesc = static_cast<const BatchDesc *>(slot.devtab);
     const int tok = prof::begin(prof_name, stream);
@@ -349,15 +369,15 @@ void release_batch()
     free_slot(g.api_slot);
     if (g.d_pow2)
         (void)hipFree(g.d_pow2);
-    if (g.d_rows_s)
-        (void)hipFree(g.d_rows_s);
+    if (g.d_spread)
+        (void)hipFree(g.d_spread);
     if (g.d_carry_nib)
         (void)hipFree(g.d_carry_nib);
     if (g.d_acc)
         (void)hipFree(g.d_acc);
     if (g.h_acc)
         (void)hipHostFree(g.h_acc);
-    g.d_pow2 = g.d_rows_s = g.d_carry_nib = g.d_acc = g.h_acc = nullptr;
+    g.d_pow2 = g.d_spread = g.d_carry_nib = g.d_acc = g.h_acc = nullptr;
     g.device = -1;
 }
 

@@ -13,15 +13,18 @@
 // partial), and every wave leaves the loop when the items run out.
 //
 // Per item, lane l produces the S values of the tile's l-th sub-range. Its
-// starting state comes from GF(2) jump-ahead done by the whole wave at once:
-// lane r holds row r of a jump matrix M and M x is one AND, two popcounts
-// and a ballot (x is uniform across the wave). The wave first jumps from
-// the stream's initial state to the tile's first position with the
-// T^(2^b) tables, then walks lane by lane with T^S, depositing each
-// lane's start. Each lane then emits 16 values per round into its own LDS
-// row (one 128-byte line), and the wave writes the 64 lines back with
-// 16-byte stores, 8 lanes per line, so every store instruction covers whole
-// lines. LDS and cross-lane operations appear only for this bookkeeping.
+// starting state comes from GF(2) jump-ahead. The wave first jumps from the
+// stream's initial state to the tile's first position with the T^(2^b)
+// tables, all lanes at once: lane r holds row r of a jump matrix M and M x
+// is one AND, two popcounts and a ballot (x is uniform across the wave).
+// Each lane m then places itself m S values further with a lane-spread
+// table: T^(m S) z is the XOR of 16 entries, one per nibble of the uniform
+// z, and the 64 lanes read 64 consecutive entries (one coalesced load per
+// nibble). Each lane then emits R values per round into its own LDS row
+// (one 128-byte line for R = 16), and the wave writes the 64 lines back
+// with 16-byte stores, 8 lanes per line, so every store instruction covers
+// whole lines. LDS and cross-lane operations appear only for this
+// bookkeeping.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -95,7 +98,7 @@ __device__ __forceinline__ uint64_t lane_carry(const uint64_t *__restrict__ tab,
 template <int S, int R>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict__ desc,
                                                     const uint64_t *__restrict__ pow2,
-                                                    const uint64_t *__restrict__ rows_s,
+                                                    const uint64_t *__restrict__ spread,
                                                     const uint64_t *__restrict__ carry_nib,
                                                     uint32_t run_items, uint32_t per_item)
 {
@@ -124,7 +127,6 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
     const uint32_t m = desc->m;
     g_req *__restrict__ reqs = (g_req *)desc->reqs;
     g_cu64 *__restrict__ states = (g_cu64 *)desc->states;
-    const uint64_t row_s = rows_s[lane];
     unsigned long long *counter =
         reinterpret_cast<unsigned long long *>(const_cast<uint64_t *>(&desc->next_item));
 
@@ -195,24 +197,36 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
             mix.mix_high = r.mix_high;
             mix.zero_fix = r.zero_fix;
             const uint64_t x0 = states ? states[gid] : init_state(mix, gid);
-            uint64_t cur = wave_jump(pow2, lane, x0, offset + (q0 - B));
-            uint64_t curpos = q0;
-            x = 0;
-            for (uint32_t l = 0; l < 64; ++l) {
-                const uint64_t ls = T0 + (uint64_t)l * S;
-                const uint64_t p = ls > B ? ls : B;
-                const uint64_t e = (ls + S) < E ? (ls + S) : E;
-                if (p >= e)
-                    continue;
-                const uint64_t delta = p - curpos;
-                if (delta == (uint64_t)S)
-                    cur = wave_matvec(row_s, cur);
-                else if (delta)
-                    cur = wave_jump(pow2, lane, cur, delta);
-                curpos = p;
-                if (lane == l)
-                    x = cur;
+            const uint64_t xq0 = wave_jump(pow2, lane, x0, offset + (q0 - B));
+            // Lanes from b on start at T0 + l S = (T0 + b S) + (l - b) S: with
+            // z the state at T0 + b S, lane l takes T^((l - b) S) z from the
+            // spread table. If the request starts inside lane l0's range, that
+            // lane takes the state at q0 itself and b = l0 + 1.
+            uint32_t b = 0, l0 = 64;
+            uint64_t z = xq0;
+            if (q0 != T0) {
+                const uint32_t d = (uint32_t)(q0 - T0); // < C
+                const uint32_t rem = d % (uint32_t)S;
+                b = d / (uint32_t)S;
+                if (rem != 0) {
+                    l0 = b++;
+                    if (b < 64)
+                        z = wave_jump(pow2, lane, xq0, (uint64_t)S - rem);
+                }
             }
+            x = 0;
+            if (lane >= b) {
+                const uint64_t *__restrict__ col = spread + (lane - b);
+                uint64_t e[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    e[q] = col[(16u * q + (uint32_t)((z >> (4 * q)) & 15u)) * 64u];
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    x ^= e[q];
+            }
+            if (lane == l0)
+                x = xq0;
         }
 
         const bool full = T0 >= B && T0 + C <= E;
@@ -292,10 +306,10 @@ hipError_t launch_batch_s(const BatchDesc *desc, const BatchTables &t, const rng
     const uint32_t run = c.run_items ? c.run_items : 1;
     if (c.row_values == 8)
         batch_kernel<S, 8><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
-            desc, t.pow2, t.rows_s, t.carry_nib, run, c.per_item);
+            desc, t.pow2, t.spread, t.carry_nib, run, c.per_item);
     else
         batch_kernel<S, 16><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
-            desc, t.pow2, t.rows_s, t.carry_nib, run, c.per_item);
+            desc, t.pow2, t.spread, t.carry_nib, run, c.per_item);
     return hipGetLastError();
 }
 

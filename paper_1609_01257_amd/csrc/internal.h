@@ -134,14 +134,17 @@ struct BatchSlot {
 bool batch_cfg_valid(const rngx_batch_cfg &c);
 // Entries of the per-S carry table: 16 nibble positions x 16 values.
 constexpr int kCarryTable = 256;
+// Entries of the per-S lane-spread table: 16 nibble positions x 16 values x
+// 64 lanes (128 KiB).
+constexpr int kSpreadTable = 16 * 16 * 64;
 // Device tables one batch launch needs, for its values-per-lane S.
 struct BatchTables {
     const uint64_t *pow2;       // T^(2^b), b < 64: 64 rows each
-    const uint64_t *rows_s;     // rows of T^S
+    const uint64_t *spread;     // T^(m S) (v << 4q) at ((16 q + v) * 64 + m)
     const uint64_t *carry_nib; // T^(63 S) (next tile, same lane) as kCarryTable nibble entries
 };
 // Device copies of the jump tables for the current device (thread-safe).
-int batch_tables_locked(const uint64_t **pow2, const uint64_t **rows_s_all, int *n_cus,
+int batch_tables_locked(const uint64_t **pow2, const uint64_t **spread_all, int *n_cus,
                         const uint64_t **carry_nib_all = nullptr);
 rngx_batch_cfg resolved_cfg(const rngx_batch_cfg &c, int n_cus);
 int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out,
