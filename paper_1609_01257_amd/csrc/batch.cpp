@@ -356,12 +356,6 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
 
 void release_slot(BatchSlot &slot) { free_slot(slot); }
 
-rngx_batch_cfg current_batch_cfg()
-{
-    std::lock_guard<std::mutex> lk(G().mu);
-    return G().cfg;
-}
-
 void release_batch()
 {
     BatchGlobals &g = G();

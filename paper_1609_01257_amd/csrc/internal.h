@@ -166,7 +166,6 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg, hipStream_t stream,
 void release_slot(BatchSlot &slot);
 void release_batch();
 void release_server(); // serve.cpp: stop the server, free its resources
-rngx_batch_cfg current_batch_cfg();
 int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *result);
 hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const BatchTables &t,
                         hipStream_t s);
