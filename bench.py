@@ -284,6 +284,10 @@ def main():
                     help="run only the headline kernel (for profiling)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched ragged-stream step (for profiling)")
+    ap.add_argument("--streaming-only", action="store_true",
+                    help="run only the paper-shaped streaming pipeline (for profiling)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving runs (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 16 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -313,6 +317,19 @@ def main():
         log("batched:", res)
         rngx.shutdown()
         print(json.dumps({"batched": res}), flush=True)
+        return
+    if args.streaming_only:
+        res = streaming(torch, rngx)
+        log("streaming:", res)
+        rngx.shutdown()
+        print(json.dumps({"streaming": res}), flush=True)
+        return
+    if args.serving_only:
+        # The plain kernel at the batched table's size, as in the full run.
+        plain = plain_run(torch, rngx, 1, 1 << 24, 438, False, 1, 5)
+        res = serving(torch, rngx, args.serve_seconds, plain["kernel_gbs"])
+        rngx.shutdown()
+        print(json.dumps({"serving": res}), flush=True)
         return
     n, iters, seed = 1 << 26, 256, 1
     log("headline: plain u64, n=2^26, iters=256, warmup=%d steps=%d" % (args.warmup, args.steps))
