@@ -342,6 +342,15 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
             slot.exec_cfg = cfg;
         }
         RNGX_HIP(hipGraphLaunch(slot.exec, stream));
+    } else if (cfg.per_item && slot.m_staged <= kSmallReqs) {
+        // Small table: it goes in the kernel's arguments, no upload.
+        SmallTable st;
+        std::memcpy(&st.desc, slot.staging, sizeof(BatchDesc));
+        std::memcpy(st.reqs, static_cast<const char *>(slot.staging) + sizeof(BatchDesc),
+                    (size_t)slot.m_staged * sizeof(BatchReq));
+        hipError_t e = launch_batch_small(cfg, st, tabs, stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "batch kernel launch");
     } else {
         const size_t bytes = sizeof(BatchDesc) + (size_t)slot.m_staged * sizeof(BatchReq);
         RNGX_HIP(hipMemcpyAsync(slot.devtab, slot.staging, bytes, hipMemcpyHostToDevice, stream));

@@ -135,6 +135,161 @@ __device__ __forceinline__ uint64_t lane_carry(const uint64_t *__restrict__ tab,
     return y;
 }
 
+// The fields of a request that one work item needs, read once per item.
+struct ItemReq {
+    uint64_t offset, length, vbase, item_begin, first_tile;
+    uint64_t *dst;
+    uint32_t gid, mix_low, mix_high, zero_fix;
+};
+
+__device__ __forceinline__ ItemReq load_req(g_req *__restrict__ reqs, uint32_t j)
+{
+    g_req &r = reqs[j];
+    ItemReq q;
+    q.offset = r.offset;
+    q.length = r.length;
+    q.vbase = r.vbase;
+    q.item_begin = r.item_begin;
+    q.first_tile = r.first_tile;
+    q.dst = r.dst;
+    q.gid = r.gid;
+    q.mix_low = r.mix_low;
+    q.mix_high = r.mix_high;
+    q.zero_fix = r.zero_fix;
+    return q;
+}
+
+// What a wave does for one work item of request r once r is known: the
+// lanes' starting states (from the stream start, or carried from the
+// previous tile of the same request), then S values per lane through LDS
+// rows and out with whole-line stores. Returns whether the tile was full,
+// in which case each lane's state ends S values past its start.
+template <int S, int R>
+__device__ __forceinline__ bool process_item(const ItemReq &r, uint64_t item, bool carry,
+                                             uint64_t &x, uint64_t *lds,
+                                             const uint64_t *carry_tab,
+                                             const uint64_t *__restrict__ pow2,
+                                             const uint64_t *__restrict__ spread,
+                                             g_cu64 *__restrict__ states, uint32_t lane)
+{
+    constexpr uint64_t C = 64ull * S;
+    constexpr int ROUND = R;
+    constexpr int LDS_ROW = lds_row(R);
+    constexpr uint32_t CPR = R / 2;     // 16-byte chunks per row
+    constexpr uint32_t RPI = 64 / CPR;  // rows per store instruction
+    const uint64_t B = r.vbase, E = r.vbase + r.length;
+    // Output address of virtual index P is obase + P (obase = dst - vbase).
+    g_u64 *__restrict__ obase =
+        (g_u64 *)(reinterpret_cast<uintptr_t>(r.dst) - B * sizeof(uint64_t));
+    const uint64_t T0 = (r.first_tile + (item - r.item_begin)) * C;
+
+    if (carry) {
+        x = lane_carry(carry_tab, x);
+    } else {
+        const uint64_t q0 = T0 > B ? T0 : B;
+        // State at q0, then each active lane's first position.
+        SeedMix mix;
+        mix.mix_low = r.mix_low;
+        mix.mix_high = r.mix_high;
+        mix.zero_fix = r.zero_fix;
+        const uint64_t x0 = states ? states[r.gid] : init_state(mix, r.gid);
+        const uint64_t xq0 = wave_jump(pow2, lane, x0, r.offset + (q0 - B));
+        // Lanes from b on start at T0 + l S = (T0 + b S) + (l - b) S: with
+        // z the state at T0 + b S, lane l takes T^((l - b) S) z from the
+        // spread table. If the request starts inside lane l0's range, that
+        // lane takes the state at q0 itself and b = l0 + 1.
+        uint32_t b = 0, l0 = 64;
+        uint64_t z = xq0;
+        if (q0 != T0) {
+            const uint32_t d = (uint32_t)(q0 - T0); // < C
+            const uint32_t rem = d % (uint32_t)S;
+            b = d / (uint32_t)S;
+            if (rem != 0) {
+                l0 = b++;
+                if (b < 64)
+                    z = wave_jump(pow2, lane, xq0, (uint64_t)S - rem);
+            }
+        }
+        x = 0;
+        if (lane >= b) {
+            const uint64_t *__restrict__ col = spread + (lane - b);
+            uint64_t e[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                e[q] = col[(16u * q + (uint32_t)((z >> (4 * q)) & 15u)) * 64u];
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                x ^= e[q];
+        }
+        if (lane == l0)
+            x = xq0;
+    }
+
+    const bool full = T0 >= B && T0 + C <= E;
+    const uint64_t my0 = T0 + (uint64_t)lane * S;
+    for (uint32_t rd = 0; rd < (uint32_t)S / ROUND; ++rd) {
+        const uint64_t p0 = my0 + (uint64_t)rd * ROUND;
+        if (full) {
+#pragma unroll
+            for (int s = 0; s < ROUND; ++s) {
+                lds[lane * LDS_ROW + s] = x;
+                x = xs_step(x);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < ROUND; ++s) {
+                const uint64_t P = p0 + s;
+                if (P >= B && P < E) {
+                    lds[lane * LDS_ROW + s] = x;
+                    x = xs_step(x);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // Lane l of store instruction i writes 16 bytes of row RPI*i + l/CPR:
+        // CPR lanes cover one row, i.e. one whole 64- or 128-byte segment.
+        const uint32_t ch = lane % CPR;
+        if (full) {
+            u64x2 v[CPR];
+#pragma unroll
+            for (uint32_t i = 0; i < CPR; ++i) {
+                const uint32_t row = RPI * i + lane / CPR;
+                v[i] = *reinterpret_cast<const u64x2 *>(&lds[row * LDS_ROW + 2u * ch]);
+            }
+            // Wave-uniform tile base plus a 32-bit lane offset (a tile is at
+            // most 512 KiB).
+            g_u64 *__restrict__ tile = obase + T0;
+#pragma unroll
+            for (uint32_t i = 0; i < CPR; ++i) {
+                const uint32_t row = RPI * i + lane / CPR;
+                const uint32_t off = row * (uint32_t)S + rd * (uint32_t)ROUND + 2u * ch;
+                *(g_u64x2 *)(tile + off) = v[i];
+            }
+        } else {
+#pragma unroll
+            for (uint32_t i = 0; i < CPR; ++i) {
+                const uint32_t row = RPI * i + lane / CPR;
+                const uint64_t P = T0 + (uint64_t)row * S + (uint64_t)rd * ROUND + 2u * ch;
+                const u64x2 v = *reinterpret_cast<const u64x2 *>(&lds[row * LDS_ROW + 2u * ch]);
+                const bool v0 = P >= B && P < E;
+                const bool v1 = P + 1 >= B && P + 1 < E;
+                if (v0 && v1)
+                    *(g_u64x2 *)(obase + P) = v;
+                else if (v0)
+                    obase[P] = v.x;
+                else if (v1)
+                    obase[P + 1] = v.y;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    return full;
+}
+
 template <int S, int R>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict__ desc,
                                                     const uint64_t *__restrict__ pow2,
@@ -142,11 +297,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
                                                     const uint64_t *__restrict__ carry_nib,
                                                     uint32_t run_items, uint32_t per_item)
 {
-    constexpr uint64_t C = 64ull * S;
-    constexpr int ROUND = R;
     constexpr int LDS_ROW = lds_row(R);
-    constexpr uint32_t CPR = R / 2;     // 16-byte chunks per row
-    constexpr uint32_t RPI = 64 / CPR;  // rows per store instruction
     // Dynamic LDS: 64 * LDS_ROW u64 per wave, then the carry table (rows
     // first keeps row addresses small enough for the LDS offset fields).
     extern __shared__ uint64_t lds_dyn[];
@@ -173,7 +324,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
     // A wave takes runs of `run_items` consecutive items. While it stays on
     // one request and the previous tile was full, every lane's state is
     // already S values past its previous start and needs C - S more steps
-    // (one per-lane product with T^(C-S)): no search, jump or lane walk.
+    // (one per-lane product with T^(C-S)): no search or jump.
     // Runs shrink towards the end of the batch (guided self-scheduling: at
     // most the items left, as last seen, over twice the number of waves), so
     // the last runs taken do not leave a long tail.
@@ -209,123 +360,50 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
             lo = per_item ? find_request(reqs, m, item, lane) : bisect_request(reqs, m, item);
             req_end = lo + 1 < m ? (uint64_t)reqs[lo + 1].item_begin : n_items;
         }
-        g_req &r = reqs[lo];
-        const uint64_t B = r.vbase, E = r.vbase + r.length;
-        // Output address of virtual index P is obase + P (obase = dst - vbase).
-        g_u64 *__restrict__ obase =
-            (g_u64 *)(reinterpret_cast<uintptr_t>(r.dst) - B * sizeof(uint64_t));
-        const uint64_t T0 = (r.first_tile + (item - r.item_begin)) * C;
-
-        if (carry) {
-            x = lane_carry(carry_tab, x);
-        } else {
-            const uint64_t q0 = T0 > B ? T0 : B;
-            const uint64_t offset = r.offset;
-            const uint32_t gid = r.gid;
-            // State at q0, then each active lane's first position.
-            SeedMix mix;
-            mix.mix_low = r.mix_low;
-            mix.mix_high = r.mix_high;
-            mix.zero_fix = r.zero_fix;
-            const uint64_t x0 = states ? states[gid] : init_state(mix, gid);
-            const uint64_t xq0 = wave_jump(pow2, lane, x0, offset + (q0 - B));
-            // Lanes from b on start at T0 + l S = (T0 + b S) + (l - b) S: with
-            // z the state at T0 + b S, lane l takes T^((l - b) S) z from the
-            // spread table. If the request starts inside lane l0's range, that
-            // lane takes the state at q0 itself and b = l0 + 1.
-            uint32_t b = 0, l0 = 64;
-            uint64_t z = xq0;
-            if (q0 != T0) {
-                const uint32_t d = (uint32_t)(q0 - T0); // < C
-                const uint32_t rem = d % (uint32_t)S;
-                b = d / (uint32_t)S;
-                if (rem != 0) {
-                    l0 = b++;
-                    if (b < 64)
-                        z = wave_jump(pow2, lane, xq0, (uint64_t)S - rem);
-                }
-            }
-            x = 0;
-            if (lane >= b) {
-                const uint64_t *__restrict__ col = spread + (lane - b);
-                uint64_t e[16];
-#pragma unroll
-                for (int q = 0; q < 16; ++q)
-                    e[q] = col[(16u * q + (uint32_t)((z >> (4 * q)) & 15u)) * 64u];
-#pragma unroll
-                for (int q = 0; q < 16; ++q)
-                    x ^= e[q];
-            }
-            if (lane == l0)
-                x = xq0;
-        }
-
-        const bool full = T0 >= B && T0 + C <= E;
-        const uint64_t my0 = T0 + (uint64_t)lane * S;
-        for (uint32_t rd = 0; rd < (uint32_t)S / ROUND; ++rd) {
-            const uint64_t p0 = my0 + (uint64_t)rd * ROUND;
-            if (full) {
-#pragma unroll
-                for (int s = 0; s < ROUND; ++s) {
-                    lds[lane * LDS_ROW + s] = x;
-                    x = xs_step(x);
-                }
-            } else {
-#pragma unroll
-                for (int s = 0; s < ROUND; ++s) {
-                    const uint64_t P = p0 + s;
-                    if (P >= B && P < E) {
-                        lds[lane * LDS_ROW + s] = x;
-                        x = xs_step(x);
-                    }
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // Lane l of store instruction i writes 16 bytes of row RPI*i + l/CPR:
-            // CPR lanes cover one row, i.e. one whole 64- or 128-byte segment.
-            const uint32_t ch = lane % CPR;
-            if (full) {
-                u64x2 v[CPR];
-#pragma unroll
-                for (uint32_t i = 0; i < CPR; ++i) {
-                    const uint32_t row = RPI * i + lane / CPR;
-                    v[i] = *reinterpret_cast<const u64x2 *>(&lds[row * LDS_ROW + 2u * ch]);
-                }
-                // Wave-uniform tile base plus a 32-bit lane offset (a tile
-                // is at most 512 KiB).
-                g_u64 *__restrict__ tile = obase + T0;
-#pragma unroll
-                for (uint32_t i = 0; i < CPR; ++i) {
-                    const uint32_t row = RPI * i + lane / CPR;
-                    const uint32_t off = row * (uint32_t)S + rd * (uint32_t)ROUND + 2u * ch;
-                    *(g_u64x2 *)(tile + off) = v[i];
-                }
-            } else {
-#pragma unroll
-                for (uint32_t i = 0; i < CPR; ++i) {
-                    const uint32_t row = RPI * i + lane / CPR;
-                    const uint64_t P = T0 + (uint64_t)row * S + (uint64_t)rd * ROUND + 2u * ch;
-                    const u64x2 v = *reinterpret_cast<const u64x2 *>(&lds[row * LDS_ROW + 2u * ch]);
-                    const bool v0 = P >= B && P < E;
-                    const bool v1 = P + 1 >= B && P + 1 < E;
-                    if (v0 && v1)
-                        *(g_u64x2 *)(obase + P) = v;
-                    else if (v0)
-                        obase[P] = v.x;
-                    else if (v1)
-                        obase[P + 1] = v.y;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
+        const ItemReq r = load_req(reqs, lo);
+        const bool full = process_item<S, R>(r, item, carry, x, lds, carry_tab, pow2, spread,
+                                             states, lane);
         // Lane l now holds the state at T0 + l*S + S when the tile was full.
         ++item;
         carry = full && item < run_end && item < req_end;
     }
+}
+
+// A batch of at most kSmallReqs requests with its table in the kernel's
+// arguments: one wave per work item, no table upload before the launch.
+template <int S, int R>
+__global__ __launch_bounds__(256) void batch_small_kernel(const SmallTable t,
+                                                          const uint64_t *__restrict__ pow2,
+                                                          const uint64_t *__restrict__ spread)
+{
+    constexpr int LDS_ROW = lds_row(R);
+    extern __shared__ uint64_t lds_dyn[];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint64_t *lds = lds_dyn + (size_t)wid * 64 * LDS_ROW;
+    const uint64_t item = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wid;
+    if (item >= t.desc.n_items)
+        return;
+    // The last request whose first item is at most this item (m is small).
+    uint32_t lo = 0;
+    for (uint32_t j = 1; j < t.desc.m; ++j)
+        if (t.reqs[j].item_begin <= item)
+            lo = j;
+    const BatchReq &q = t.reqs[lo];
+    ItemReq r;
+    r.offset = q.offset;
+    r.length = q.length;
+    r.vbase = q.vbase;
+    r.item_begin = q.item_begin;
+    r.first_tile = q.first_tile;
+    r.dst = q.dst;
+    r.gid = q.gid;
+    r.mix_low = q.mix_low;
+    r.mix_high = q.mix_high;
+    r.zero_fix = q.zero_fix;
+    uint64_t x = 0;
+    (void)process_item<S, R>(r, item, false, x, lds, nullptr, pow2, spread,
+                             (g_cu64 *)t.desc.states, lane);
 }
 
 template <int S>
@@ -341,6 +419,20 @@ hipError_t launch_batch_s(const BatchDesc *desc, const BatchTables &t, const rng
     else
         batch_kernel<S, 16><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
             desc, t.pow2, t.spread, t.carry_nib, run, c.per_item);
+    return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_batch_small_s(const SmallTable &tab, const BatchTables &t,
+                                const rngx_batch_cfg &c, hipStream_t s)
+{
+    const size_t lds_bytes = (size_t)c.waves_per_block * 64 * lds_row(c.row_values) * 8;
+    if (c.row_values == 8)
+        batch_small_kernel<S, 8><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
+            tab, t.pow2, t.spread);
+    else
+        batch_small_kernel<S, 16><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
+            tab, t.pow2, t.spread);
     return hipGetLastError();
 }
 
@@ -393,6 +485,20 @@ hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const 
     case 256: return launch_batch_s<256>(desc, t, cfg, s);
     case 512: return launch_batch_s<512>(desc, t, cfg, s);
     default: return launch_batch_s<1024>(desc, t, cfg, s);
+    }
+}
+
+hipError_t launch_batch_small(const rngx_batch_cfg &cfg, const SmallTable &tab,
+                              const BatchTables &t, hipStream_t s)
+{
+    switch (cfg.values_per_lane) {
+    case 16: return launch_batch_small_s<16>(tab, t, cfg, s);
+    case 32: return launch_batch_small_s<32>(tab, t, cfg, s);
+    case 64: return launch_batch_small_s<64>(tab, t, cfg, s);
+    case 128: return launch_batch_small_s<128>(tab, t, cfg, s);
+    case 256: return launch_batch_small_s<256>(tab, t, cfg, s);
+    case 512: return launch_batch_small_s<512>(tab, t, cfg, s);
+    default: return launch_batch_small_s<1024>(tab, t, cfg, s);
     }
 }
 

@@ -118,6 +118,14 @@ struct BatchDesc {
 };
 static_assert(sizeof(BatchDesc) == 64, "BatchDesc layout");
 
+// A batch of at most kSmallReqs requests travels in the kernel's arguments
+// (1,088 bytes) instead of being uploaded: one launch, no copy before it.
+constexpr uint32_t kSmallReqs = 16;
+struct SmallTable {
+    BatchDesc desc;
+    BatchReq reqs[kSmallReqs];
+};
+
 // A staging/upload slot for one batch in flight (batch.cpp).
 struct BatchSlot {
     uint32_t capacity = 0;    // requests the buffers hold (power of two)
@@ -169,6 +177,8 @@ void release_server(); // serve.cpp: stop the server, free its resources
 int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *result);
 hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const BatchTables &t,
                         hipStream_t s);
+hipError_t launch_batch_small(const rngx_batch_cfg &cfg, const SmallTable &tab,
+                              const BatchTables &t, hipStream_t s);
 // Checksum sum_i data[i] * (2 i + 1) mod 2^64 into *acc (device, pre-zeroed).
 hipError_t launch_checksum(const uint64_t *data, uint64_t n, uint64_t *acc, hipStream_t s);
 

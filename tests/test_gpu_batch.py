@@ -62,6 +62,18 @@ def test_every_per_item_config(oracle, S, wpb, graph, row):
     assert np.array_equal(_run(_reqs(r), r.total), exp)
 
 
+@pytest.mark.parametrize("m", [1, 2, 7, 15, 16, 17])
+@pytest.mark.parametrize("S", [16, 64, 256])
+def test_small_tables_in_kernel_arguments(oracle, m, S):
+    # Up to 16 requests, one wave per item and no graph: the request table
+    # travels in the kernel's arguments (17 takes the uploaded-table path).
+    r = inputs.ragged_requests(m=m, seed=500 + m, max_len=90000, max_offset=10**7)
+    exp = oracle.generate_batch(_oracle_reqs(oracle, r))
+    for row in (8, 16):
+        rngx.set_batch_cfg(S, 4, 0, False, row, 1, True)
+        assert np.array_equal(_run(_reqs(r), r.total), exp), row
+
+
 def test_per_item_graph_follows_item_count(oracle):
     # The captured graph is re-captured when the item count changes and
     # reused when it does not; every replay checked against the oracle.
