@@ -44,7 +44,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB):
             build(force=True)
         L = ctypes.CDLL(_LIB)
         u32, u64, p = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
@@ -62,6 +62,12 @@ def lib():
         L.oracle_generate.restype = u64
         L.oracle_generate_u32.argtypes = [u64, u32, u64, u32, p]
         L.oracle_generate_u32.restype = u64
+        L.oracle_scramble.argtypes = [u64]
+        L.oracle_scramble.restype = u64
+        L.oracle_generate_star.argtypes = [u64, u32, u64, u32, p]
+        L.oracle_generate_star.restype = u64
+        L.oracle_generate_star_u32.argtypes = [u64, u32, u64, u32, p]
+        L.oracle_generate_star_u32.restype = u64
         L.oracle_generate_batch.argtypes = [p, u32, p]
         L.oracle_generate_batch.restype = u64
         L.oracle_hash_low_range.argtypes = [u32, u64, p]
@@ -121,6 +127,29 @@ def generate_u32(seed: int, n: int, n_iters: int, cursor: int = 0) -> np.ndarray
     zeros = lib().oracle_generate_u32(seed, n, cursor, n_iters, _ptr(out))
     if zeros:
         raise AssertionError("oracle produced %d zero values" % zeros)
+    return out
+
+
+def scramble(x: int) -> int:
+    """The scrambled variant's output word for state x (xorshift* reading)."""
+    return lib().oracle_scramble(x)
+
+
+def generate_star(seed: int, n: int, n_iters: int, cursor: int = 0) -> np.ndarray:
+    """Scrambled plain output: out[k, g] = scramble(value(seed, g, cursor + k))."""
+    out = np.empty((n_iters, n), dtype=np.uint64)
+    zeros = lib().oracle_generate_star(seed, n, cursor, n_iters, _ptr(out))
+    if zeros:
+        raise AssertionError("oracle produced %d zero values" % zeros)
+    return out
+
+
+def generate_star_u32(seed: int, n: int, n_iters: int, cursor: int = 0) -> np.ndarray:
+    """High 32-bit halves of :func:`generate_star`."""
+    out = np.empty((n_iters, n), dtype=np.uint32)
+    zeros = lib().oracle_generate_star_u32(seed, n, cursor, n_iters, _ptr(out))
+    if zeros:
+        raise AssertionError("oracle produced %d zero states" % zeros)
     return out
 
 

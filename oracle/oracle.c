@@ -26,6 +26,12 @@
  *    the .y half of a uint2 that the rng kernel then reads as one ulong, i.e.
  *    the state is (high << 32) | low on a little-endian device.
  *
+ * The scrambled variant (oracle_scramble, oracle_generate_star*) follows
+ * the paper's remark that a more complex generator would cost nothing; its
+ * reading (the xorshift* output multiplication) is stated where it is
+ * defined, and it is pinned by linear complexity, the odd multiplier's
+ * inverse and the shared state sequence.
+ *
  * Pins: the oracle's own tests check it against hand-traced values, the
  * full-period property of the (21,35,4) xorshift over GF(2), bijectivity of
  * both 32-bit hashes, the never-zero invariant, concatenation and transpose
@@ -170,6 +176,65 @@ uint64_t oracle_generate_u32(uint64_t seed, uint32_t n, uint64_t cursor,
             if (st[g] == 0u)
                 ++zeros;
             out[(size_t)k * n + g] = (uint32_t)(st[g] & 0xffffffffu);
+            st[g] = oracle_rng_step(st[g]);
+        }
+    }
+    free(st);
+    return zeros;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Scrambled output variant. The paper observes (discussing the queue chart   */
+/* of Fig. 5) that its generator kernels are much shorter than the transfers, */
+/* so a more complex generator would cost nothing and give better numbers.    */
+/* Reading: the xorshift* construction (S. Vigna, "An experimental           */
+/* exploration of Marsaglia's xorshift generators, scrambled", ACM TOMS      */
+/* 2016) applied to this generator. The state sequence is unchanged (same     */
+/* seeding, same (21,35,4) steps, same cursor); only the emitted word        */
+/* changes: the state times the odd constant 2685821657736338717 (that       */
+/* paper's multiplier) modulo 2^64. An odd multiplier is a bijection of the  */
+/* 64-bit words, so periods and the never-zero property carry over, while    */
+/* the output bits stop being GF(2)-linear functions of the state. The       */
+/* 32-bit form keeps the high half of the product, as that paper advises    */
+/* (the low half of a product only depends on the low halves).               */
+/* ------------------------------------------------------------------------- */
+uint64_t oracle_scramble(uint64_t x)
+{
+    return x * 2685821657736338717ull;
+}
+
+uint64_t oracle_generate_star(uint64_t seed, uint32_t n, uint64_t cursor,
+                              uint32_t n_iters, uint64_t *out)
+{
+    uint64_t zeros = 0;
+    uint64_t *st = seeded_states(seed, n, cursor);
+    if (!st)
+        return UINT64_MAX;
+    for (uint32_t k = 0; k < n_iters; ++k) {
+        for (uint32_t g = 0; g < n; ++g) {
+            const uint64_t v = oracle_scramble(st[g]);
+            if (v == 0u)
+                ++zeros;
+            out[(size_t)k * n + g] = v;
+            st[g] = oracle_rng_step(st[g]);
+        }
+    }
+    free(st);
+    return zeros;
+}
+
+uint64_t oracle_generate_star_u32(uint64_t seed, uint32_t n, uint64_t cursor,
+                                  uint32_t n_iters, uint32_t *out)
+{
+    uint64_t zeros = 0;
+    uint64_t *st = seeded_states(seed, n, cursor);
+    if (!st)
+        return UINT64_MAX;
+    for (uint32_t k = 0; k < n_iters; ++k) {
+        for (uint32_t g = 0; g < n; ++g) {
+            if (st[g] == 0u)
+                ++zeros;
+            out[(size_t)k * n + g] = (uint32_t)(oracle_scramble(st[g]) >> 32);
             st[g] = oracle_rng_step(st[g]);
         }
     }
