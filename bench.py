@@ -367,6 +367,16 @@ def main():
         result["u32"] = {"out_gbs": round(h32["out_gbs"], 1),
                          "kernel_gbs": round(h32["kernel_gbs"], 1),
                          "frac_hbm": round(h32["kernel_gbs"] / HBM_PEAK_GBS, 4)}
+        log("scrambled variant, headline shape")
+        rngx.set_scrambler(rngx.SCRAMBLE_STAR)
+        try:
+            hs = plain_run(torch, rngx, seed, n, iters, False, 1, max(3, args.steps // 4))
+        finally:
+            rngx.set_scrambler(rngx.SCRAMBLE_NONE)
+        result["scrambled"] = {"out_gbs": round(hs["out_gbs"], 1),
+                               "kernel_gbs": round(hs["kernel_gbs"], 1),
+                               "frac_hbm": round(hs["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                               "vs_plain": round(hs["kernel_gbs"] / head["kernel_gbs"], 4)}
         if not args.no_sweep:
             result["sweep"] = sweep(torch, rngx, 3)
         log("batched ragged streams")

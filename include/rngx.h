@@ -141,6 +141,22 @@ typedef struct rngx_launch {
 int rngx_set_launch(int u32, const rngx_launch *cfg);
 int rngx_get_launch(int u32, rngx_launch *cfg);
 
+/* Output scrambler of the plain path (rngx_generate, rngx_generate_u32 and
+ * rngx_stream_to_host; process-wide, kept across rngx_init). The paper
+ * notes, discussing Fig. 5, that its generator kernels are much shorter
+ * than the transfers, so a more complex generator would cost nothing.
+ * RNGX_SCRAMBLE_NONE (default): the paper's generator, the state is the
+ *   output (its low half for 32-bit output).
+ * RNGX_SCRAMBLE_STAR: the xorshift* construction (Vigna, 2016) on the same
+ *   states: each output is the state times 2685821657736338717 modulo 2^64
+ *   (its high half for 32-bit output). The states, the cursor, seeding,
+ *   checkpoints and the batched and served paths are unchanged.
+ * Errors: RNGX_E_INVAL for an unknown scrambler or a NULL pointer. */
+#define RNGX_SCRAMBLE_NONE 0
+#define RNGX_SCRAMBLE_STAR 1
+int rngx_set_scrambler(int scrambler);
+int rngx_get_scrambler(int *scrambler);
+
 /* ------------------------------------------------------------------------ */
 /* Streaming to host memory (Section 5, Fig. 2)                              */
 /* ------------------------------------------------------------------------ */

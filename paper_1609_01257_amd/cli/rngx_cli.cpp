@@ -10,9 +10,11 @@
 // rngx_stream_to_host; the host writes each step out while the device works
 // on the next ones (host_slots page-locked slots).
 //
-// Usage: rngx_cli [-s seed] [-u] [-k iters_per_step] [-h host_slots] n i
+// Usage: rngx_cli [-s seed] [-u] [-x] [-k iters_per_step] [-h host_slots] n i
 //   -s seed   64-bit seed (decimal or 0x hex), default 0;
-//   -u        write the low 32 bits of each value (4 * n * i bytes);
+//   -u        write 32-bit values (4 * n * i bytes);
+//   -x        the scrambled variant (each value times 2685821657736338717
+//             modulo 2^64, the high half with -u) instead of the states;
 //   -k        iterations per generation launch and copy, default 1;
 //   -h        host slots, default 2.
 // Exit status 0 on success, 1 on a library or I/O error (message on stderr),
@@ -35,7 +37,7 @@ int consume(void *user, uint64_t, const void *values, size_t bytes)
 
 int usage(const char *msg)
 {
-    std::fprintf(stderr, "rngx_cli: %s\nusage: rngx_cli [-s seed] [-u] [-k iters_per_step] "
+    std::fprintf(stderr, "rngx_cli: %s\nusage: rngx_cli [-s seed] [-u] [-x] [-k iters_per_step] "
                          "[-h host_slots] n i\n", msg);
     return 2;
 }
@@ -64,11 +66,13 @@ int fail(const char *what, int rc)
 int main(int argc, char **argv)
 {
     unsigned long long seed = 0, k = 1, slots = 2, n = 0, iters = 0;
-    int u32 = 0, pos = 0;
+    int u32 = 0, star = 0, pos = 0;
     const char *args[2] = {nullptr, nullptr};
     for (int a = 1; a < argc; ++a) {
         if (!std::strcmp(argv[a], "-u")) {
             u32 = 1;
+        } else if (!std::strcmp(argv[a], "-x")) {
+            star = 1;
         } else if (!std::strcmp(argv[a], "-s") || !std::strcmp(argv[a], "-k") ||
                    !std::strcmp(argv[a], "-h")) {
             if (a + 1 >= argc)
@@ -95,7 +99,10 @@ int main(int argc, char **argv)
         return usage("a step of k iterations times host slots exceeds 1 TiB");
     const size_t step_bytes = (size_t)k * n * esize;
 
-    int rc = rngx_init(seed, (uint32_t)n);
+    int rc = rngx_set_scrambler(star ? RNGX_SCRAMBLE_STAR : RNGX_SCRAMBLE_NONE);
+    if (rc)
+        return fail("rngx_set_scrambler", rc);
+    rc = rngx_init(seed, (uint32_t)n);
     if (rc)
         return fail("rngx_init", rc);
     void *dev[2] = {nullptr, nullptr}, *host = nullptr;

@@ -133,7 +133,8 @@ int generate_locked(Generator &c, uint32_t n_iters, void *out, hipStream_t s, bo
         return rc;
     RNGX_HIP(hipStreamWaitEvent(s, c.state_ready, 0));
     const int tok = prof::begin("RNG_KERNEL", s);
-    hipError_t e = launch_gen(u32 ? c.cfg32 : c.cfg64, u32, c.state, c.n, n_iters, out, s);
+    hipError_t e = launch_gen(u32 ? c.cfg32 : c.cfg64, u32, c.scrambler == RNGX_SCRAMBLE_STAR,
+                              c.state, c.n, n_iters, out, s);
     prof::end(tok, s);
     if (e != hipSuccess)
         return hip_fail(e, "rng kernel launch");
@@ -290,6 +291,28 @@ int rngx_set_launch(int u32, const rngx_launch *cfg)
                          "rngx_set_launch: block must be 64..1024 in steps of 64, chunks 1, 2 "
                          "or 4, nontemporal 0 or 1");
     (u32 ? c.cfg32 : c.cfg64) = *cfg;
+    return RNGX_OK;
+}
+
+int rngx_set_scrambler(int scrambler)
+{
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    clear_error();
+    if (scrambler != RNGX_SCRAMBLE_NONE && scrambler != RNGX_SCRAMBLE_STAR)
+        return set_error(RNGX_E_INVAL, "rngx_set_scrambler: unknown scrambler %d", scrambler);
+    c.scrambler = scrambler;
+    return RNGX_OK;
+}
+
+int rngx_get_scrambler(int *scrambler)
+{
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    clear_error();
+    if (!scrambler)
+        return set_error(RNGX_E_INVAL, "rngx_get_scrambler: NULL");
+    *scrambler = c.scrambler;
     return RNGX_OK;
 }
 

@@ -189,7 +189,7 @@ void power_rows(uint64_t k, uint64_t *rows_out);
 
 // ---- kernel launchers (kernels.hip) ---------------------------------------
 hipError_t launch_init(uint64_t *state, uint32_t n, const SeedMix &mix, hipStream_t s);
-hipError_t launch_gen(const rngx_launch &cfg, bool u32, uint64_t *state, uint32_t n,
+hipError_t launch_gen(const rngx_launch &cfg, bool u32, bool star, uint64_t *state, uint32_t n,
                       uint32_t iters, void *out, hipStream_t s);
 bool launch_cfg_valid(const rngx_launch &cfg);
 // copy.hip: device buffer -> page-locked host memory (device-mapped address).
@@ -214,6 +214,7 @@ struct Generator {
     hipEvent_t gen_done[2] = {nullptr, nullptr};
     hipEvent_t copy_done[2] = {nullptr, nullptr};
     int copy_mode = RNGX_COPY_KERNEL;
+    int scrambler = RNGX_SCRAMBLE_NONE; // output word of the plain path
     // 16 workgroups saturate PCIe 5.0 x16 on MI355X and slow the overlapping
     // generation kernel least (measured: 16 to 256 all within 4 %).
     uint32_t copy_blocks = 16;

@@ -30,18 +30,42 @@ __global__ __launch_bounds__(256) void init_kernel(uint64_t *__restrict__ state,
         state[g] = init_state(mix, (uint32_t)g);
 }
 
+// The word emitted for state x. The paper's generator emits the state (its
+// low half for 32-bit output). The scrambled variant emits the state times
+// 2685821657736338717 modulo 2^64 (the xorshift* multiplier of Vigna, 2016),
+// its high half for 32-bit output; the state sequence is the same.
+constexpr uint64_t kStarMultiplier = 2685821657736338717ull;
+template <typename T, bool STAR> __device__ __forceinline__ T emit(uint64_t x);
+template <> __device__ __forceinline__ uint64_t emit<uint64_t, false>(uint64_t x) { return x; }
+template <> __device__ __forceinline__ uint32_t emit<uint32_t, false>(uint64_t x)
+{
+    return (uint32_t)x;
+}
+template <> __device__ __forceinline__ uint64_t emit<uint64_t, true>(uint64_t x)
+{
+    return x * kStarMultiplier;
+}
+template <> __device__ __forceinline__ uint32_t emit<uint32_t, true>(uint64_t x)
+{
+    return (uint32_t)((x * kStarMultiplier) >> 32);
+}
+
 template <typename T> struct Vec16;
 template <> struct Vec16<uint64_t> {
     static constexpr int E = 2;
     typedef u64x2 type;
-    __device__ static __forceinline__ type pack(const uint64_t *x) { return type{x[0], x[1]}; }
+    template <bool STAR> __device__ static __forceinline__ type pack(const uint64_t *x)
+    {
+        return type{emit<uint64_t, STAR>(x[0]), emit<uint64_t, STAR>(x[1])};
+    }
 };
 template <> struct Vec16<uint32_t> {
     static constexpr int E = 4;
     typedef u32x4 type;
-    __device__ static __forceinline__ type pack(const uint64_t *x)
+    template <bool STAR> __device__ static __forceinline__ type pack(const uint64_t *x)
     {
-        return type{(uint32_t)x[0], (uint32_t)x[1], (uint32_t)x[2], (uint32_t)x[3]};
+        return type{emit<uint32_t, STAR>(x[0]), emit<uint32_t, STAR>(x[1]),
+                    emit<uint32_t, STAR>(x[2]), emit<uint32_t, STAR>(x[3])};
     }
 };
 
@@ -55,7 +79,7 @@ template <bool NT, typename VT> __device__ __forceinline__ void store16(VT *p, V
 
 // P chunk columns per lane; NT: non-temporal stores; ALIGNED: every row
 // start is 16-byte aligned (out 16-byte aligned and n*sizeof(T) % 16 == 0).
-template <typename T, int P, bool NT, bool ALIGNED>
+template <typename T, int P, bool NT, bool ALIGNED, bool STAR>
 __global__ __launch_bounds__(1024) void gen_kernel(uint64_t *__restrict__ state, uint32_t n,
                                                    uint32_t iters, T *__restrict__ out)
 {
@@ -85,11 +109,12 @@ __global__ __launch_bounds__(1024) void gen_kernel(uint64_t *__restrict__ state,
             for (int p = 0; p < P; ++p) {
                 const uint64_t g = wbase + (uint64_t)p * 64 * E + (uint64_t)lane * E;
                 if (al) {
-                    store16<NT>(reinterpret_cast<typename VT::type *>(row + g), VT::pack(x[p]));
+                    store16<NT>(reinterpret_cast<typename VT::type *>(row + g),
+                                VT::template pack<STAR>(x[p]));
                 } else {
 #pragma unroll
                     for (int e = 0; e < E; ++e)
-                        row[g + e] = (T)x[p][e];
+                        row[g + e] = emit<T, STAR>(x[p][e]);
                 }
 #pragma unroll
                 for (int e = 0; e < E; ++e)
@@ -124,7 +149,7 @@ __global__ __launch_bounds__(1024) void gen_kernel(uint64_t *__restrict__ state,
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 if ((uint32_t)e < cnt[p])
-                    row[g + e] = (T)x[p][e];
+                    row[g + e] = emit<T, STAR>(x[p][e]);
                 x[p][e] = xs_step(x[p][e]);
             }
         }
@@ -139,38 +164,39 @@ __global__ __launch_bounds__(1024) void gen_kernel(uint64_t *__restrict__ state,
     }
 }
 
-template <typename T, int P, bool NT, bool AL>
+template <typename T, int P, bool NT, bool AL, bool STAR>
 hipError_t launch_gen_t(uint32_t block, uint64_t *state, uint32_t n, uint32_t iters, T *out,
                         hipStream_t s)
 {
     constexpr uint64_t WAVE_ITEMS = 64ull * P * Vec16<T>::E;
     const uint64_t waves = (n + WAVE_ITEMS - 1) / WAVE_ITEMS;
     const uint64_t blocks = (waves * 64 + block - 1) / block;
-    gen_kernel<T, P, NT, AL><<<dim3((uint32_t)blocks), dim3(block), 0, s>>>(state, n, iters, out);
+    gen_kernel<T, P, NT, AL, STAR>
+        <<<dim3((uint32_t)blocks), dim3(block), 0, s>>>(state, n, iters, out);
     return hipGetLastError();
 }
 
-template <typename T, int P>
+template <typename T, int P, bool STAR>
 hipError_t launch_gen_p(const rngx_launch &cfg, bool al, uint64_t *state, uint32_t n,
                         uint32_t iters, T *out, hipStream_t s)
 {
     if (cfg.nontemporal)
-        return al ? launch_gen_t<T, P, true, true>(cfg.block, state, n, iters, out, s)
-                  : launch_gen_t<T, P, true, false>(cfg.block, state, n, iters, out, s);
-    return al ? launch_gen_t<T, P, false, true>(cfg.block, state, n, iters, out, s)
-              : launch_gen_t<T, P, false, false>(cfg.block, state, n, iters, out, s);
+        return al ? launch_gen_t<T, P, true, true, STAR>(cfg.block, state, n, iters, out, s)
+                  : launch_gen_t<T, P, true, false, STAR>(cfg.block, state, n, iters, out, s);
+    return al ? launch_gen_t<T, P, false, true, STAR>(cfg.block, state, n, iters, out, s)
+              : launch_gen_t<T, P, false, false, STAR>(cfg.block, state, n, iters, out, s);
 }
 
-template <typename T>
+template <typename T, bool STAR>
 hipError_t launch_gen_typed(const rngx_launch &cfg, uint64_t *state, uint32_t n, uint32_t iters,
                             T *out, hipStream_t s)
 {
     const bool al = (reinterpret_cast<uintptr_t>(out) & 15u) == 0 &&
                     ((uint64_t)n * sizeof(T)) % 16u == 0;
     switch (cfg.chunks) {
-    case 1: return launch_gen_p<T, 1>(cfg, al, state, n, iters, out, s);
-    case 2: return launch_gen_p<T, 2>(cfg, al, state, n, iters, out, s);
-    default: return launch_gen_p<T, 4>(cfg, al, state, n, iters, out, s);
+    case 1: return launch_gen_p<T, 1, STAR>(cfg, al, state, n, iters, out, s);
+    case 2: return launch_gen_p<T, 2, STAR>(cfg, al, state, n, iters, out, s);
+    default: return launch_gen_p<T, 4, STAR>(cfg, al, state, n, iters, out, s);
     }
 }
 
@@ -192,12 +218,16 @@ hipError_t launch_init(uint64_t *state, uint32_t n, const SeedMix &mix, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_gen(const rngx_launch &cfg, bool u32, uint64_t *state, uint32_t n,
+hipError_t launch_gen(const rngx_launch &cfg, bool u32, bool star, uint64_t *state, uint32_t n,
                       uint32_t iters, void *out, hipStream_t s)
 {
+    uint32_t *o32 = static_cast<uint32_t *>(out);
+    uint64_t *o64 = static_cast<uint64_t *>(out);
     if (u32)
-        return launch_gen_typed<uint32_t>(cfg, state, n, iters, static_cast<uint32_t *>(out), s);
-    return launch_gen_typed<uint64_t>(cfg, state, n, iters, static_cast<uint64_t *>(out), s);
+        return star ? launch_gen_typed<uint32_t, true>(cfg, state, n, iters, o32, s)
+                    : launch_gen_typed<uint32_t, false>(cfg, state, n, iters, o32, s);
+    return star ? launch_gen_typed<uint64_t, true>(cfg, state, n, iters, o64, s)
+                : launch_gen_typed<uint64_t, false>(cfg, state, n, iters, o64, s);
 }
 
 } // namespace rngx

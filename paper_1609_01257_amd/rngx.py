@@ -24,6 +24,8 @@ COPY_KERNEL = 0
 COPY_RUNTIME = 1
 EXPORT_TABLE = 0
 EXPORT_TRACE = 1
+SCRAMBLE_NONE = 0
+SCRAMBLE_STAR = 1
 
 CONSUME_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                               ctypes.c_size_t)
@@ -107,6 +109,8 @@ _SIGS = {
     "rngx_generate_u32": ([_u32, _p, _p], _int),
     "rngx_info": ([_p, _p, _p], _int),
     "rngx_get_state": ([_p, _u32, _p, _p], _int),
+    "rngx_set_scrambler": ([_int], _int),
+    "rngx_get_scrambler": ([_p], _int),
     "rngx_set_state": ([_u64, _p, _u32, _u64], _int),
     "rngx_shutdown": ([], _int),
     "rngx_last_error": ([], ctypes.c_char_p),
@@ -212,6 +216,17 @@ def info():
     s, n, c = _u64(), _u32(), _u64()
     _check(lib().rngx_info(ctypes.byref(s), ctypes.byref(n), ctypes.byref(c)))
     return s.value, n.value, c.value
+
+
+def set_scrambler(scrambler: int):
+    """Output word of the plain path: SCRAMBLE_NONE (the paper's) or SCRAMBLE_STAR."""
+    _check(lib().rngx_set_scrambler(scrambler))
+
+
+def get_scrambler() -> int:
+    v = ctypes.c_int()
+    _check(lib().rngx_get_scrambler(ctypes.byref(v)))
+    return v.value
 
 
 def get_state():

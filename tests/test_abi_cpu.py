@@ -65,6 +65,17 @@ def test_checkpoint_argument_errors_without_gpu():
     assert "state 2 is 0" in rngx.last_error()
 
 
+def test_scrambler_validation_without_gpu():
+    L = rngx.lib()
+    assert L.rngx_set_scrambler(2) == rngx.RNGX_E_INVAL
+    assert L.rngx_set_scrambler(-1) == rngx.RNGX_E_INVAL
+    assert L.rngx_get_scrambler(None) == rngx.RNGX_E_INVAL
+    rngx.set_scrambler(rngx.SCRAMBLE_STAR)
+    assert rngx.get_scrambler() == rngx.SCRAMBLE_STAR
+    rngx.set_scrambler(rngx.SCRAMBLE_NONE)
+    assert rngx.get_scrambler() == rngx.SCRAMBLE_NONE
+
+
 def test_set_launch_validation():
     for bad in [(32, 1, 0), (1088, 1, 0), (100, 1, 0), (256, 3, 0), (256, 0, 0), (256, 1, 2)]:
         cfg = rngx.Launch(*bad)

@@ -39,3 +39,13 @@ def test_stream_matches_oracle(oracle, args, seed, n, i, u32):
     assert r.returncode == 0, r.stderr.decode()
     exp = (oracle.generate_u32 if u32 else oracle.generate)(seed, n, i)
     assert r.stdout == exp.tobytes()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("u32", [False, True])
+def test_scrambled_stream_matches_oracle(oracle, u32):
+    args = ["-x", "-s", 5, "-k", 2, 3001, 7] + (["-u"] if u32 else [])
+    r = _run(*args)
+    assert r.returncode == 0, r.stderr.decode()
+    exp = (oracle.generate_star_u32 if u32 else oracle.generate_star)(5, 3001, 7)
+    assert r.stdout == exp.tobytes()

@@ -252,3 +252,52 @@ def test_set_state_from_oracle_states(oracle):
     assert c == 1004 and np.array_equal(st, oracle.generate(seed, n, 1, cursor=1004).ravel())
     big = np.empty(n + 1, dtype=np.uint64)
     assert rngx.lib().rngx_get_state(big.ctypes.data, n + 1, None, None) == rngx.RNGX_E_INVAL
+
+
+@pytest.fixture
+def star():
+    rngx.set_scrambler(rngx.SCRAMBLE_STAR)
+    yield
+    rngx.set_scrambler(rngx.SCRAMBLE_NONE)
+
+
+@pytest.mark.parametrize("u32", [False, True])
+@pytest.mark.parametrize("n", [1, 3, 64, 65, 1025, 100003])
+def test_scrambled_output_matches_oracle(oracle, star, n, u32):
+    for iters, offset, seed in [(1, 0, 5), (4, 1, 0), (3, 0, 2**64 - 1)]:
+        got = run(seed, n, iters, u32=u32, offset=offset)
+        exp = (oracle.generate_star_u32 if u32 else oracle.generate_star)(seed, n, iters)
+        assert np.array_equal(got, exp), (n, iters, offset, seed)
+
+
+@pytest.mark.parametrize("u32", [False, True])
+def test_scrambled_every_launch_config(oracle, star, u32):
+    n, iters, seed = 20011, 3, 9
+    exp = (oracle.generate_star_u32 if u32 else oracle.generate_star)(seed, n, iters)
+    default = rngx.get_launch(u32)
+    try:
+        for block, chunks, nt in itertools.product([64, 256, 1024], [1, 2, 4], [0, 1]):
+            rngx.set_launch(u32, block, chunks, nt)
+            assert np.array_equal(run(seed, n, iters, u32=u32), exp), (block, chunks, nt)
+    finally:
+        rngx.set_launch(u32, default["block"], default["chunks"], default["nontemporal"])
+
+
+def test_scrambler_switch_keeps_the_state_sequence(oracle):
+    # The scrambler changes only the emitted words: switching it between
+    # calls continues the same streams.
+    seed, n = 31, 777
+    rngx.init(seed, n)
+    a = torch.empty(2 * n, dtype=torch.int64, device="cuda")
+    b = torch.empty(3 * n, dtype=torch.int64, device="cuda")
+    rngx.generate(2, a)
+    rngx.set_scrambler(rngx.SCRAMBLE_STAR)
+    try:
+        rngx.generate(3, b)
+    finally:
+        rngx.set_scrambler(rngx.SCRAMBLE_NONE)
+    torch.cuda.synchronize()
+    assert np.array_equal(_u64(a).reshape(2, n), oracle.generate(seed, n, 2))
+    assert np.array_equal(_u64(b).reshape(3, n), oracle.generate_star(seed, n, 3, cursor=2))
+    st, _, c = rngx.get_state()
+    assert c == 5 and np.array_equal(st, oracle.generate(seed, n, 1, cursor=5).ravel())

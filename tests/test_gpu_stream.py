@@ -211,3 +211,16 @@ def test_profile_export_of_a_streamed_run(tmp_path):
     rngx.profile_export(str(trace), rngx.EXPORT_TRACE)
     spans = [x for x in json.loads(trace.read_text())["traceEvents"] if x["ph"] == "X"]
     assert len(spans) == len(rows)
+
+
+def test_scrambled_stream_matches_oracle(oracle):
+    seed, n, R, steps = 12, 4099, 2, 5
+    rngx.init(seed, n)
+    dev0, dev1, host = _buffers(n, R, steps)
+    rngx.set_scrambler(rngx.SCRAMBLE_STAR)
+    try:
+        rngx.stream_to_host(steps, R, dev0, dev1, host, steps)
+    finally:
+        rngx.set_scrambler(rngx.SCRAMBLE_NONE)
+    got = host.numpy().view(np.uint64).reshape(steps * R, n)
+    assert np.array_equal(got, oracle.generate_star(seed, n, steps * R))
