@@ -75,8 +75,9 @@ int rngx_init(uint64_t seed, uint32_t n_states);
  * out: device memory of at least 8 * n_states * n_iters bytes, 8-byte
  *      aligned (16-byte alignment and an even n_states give the fastest
  *      stores). n_iters == 0 is a successful no-op.
- * Errors: RNGX_E_NOINIT; RNGX_E_INVAL (out NULL or misaligned, or the byte
- * count overflows size_t); RNGX_E_HIP. */
+ * Errors: RNGX_E_NOINIT; RNGX_E_INVAL (out NULL or misaligned, the byte
+ * count overflows size_t, or the cursor would pass value number 2^64 - 1);
+ * RNGX_E_HIP. */
 int rngx_generate(uint32_t n_iters, uint64_t *out, void *stream);
 
 /* As rngx_generate, writing the low 32 bits of each value:
@@ -235,7 +236,8 @@ typedef struct rngx_req {
  * reqs: m requests in host memory (zero-length requests produce nothing).
  * out:  device memory of out_cap uint64 values, 16-byte aligned.
  * Errors: RNGX_E_INVAL (NULL reqs with m > 0, NULL or misaligned out, a
- * nonzero reserved field, total length above out_cap or overflowing);
+ * nonzero reserved field, a request running past value number 2^64 - 1
+ * (offset + length > 2^64), total length above out_cap or overflowing);
  * RNGX_E_NOMEM; RNGX_E_HIP. */
 int rngx_generate_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_t out_cap,
                         void *stream);
@@ -322,8 +324,11 @@ int rngx_jump_ahead(uint64_t state, uint64_t k, uint64_t *out);
  * memory and a launch slot are free.
  * pool: caller-owned device memory of pool_bytes bytes, 256-byte aligned,
  *       kept alive until rngx_serve_stop; results are written into it.
- * Uses the current batch configuration (values_per_lane, waves_per_block),
- * launched directly with a grid fitted to each batch.
+ * Batches are launched directly (no graph) with a schedule chosen by their
+ * size, independent of the batch configuration: up to 2^20 values, one wave
+ * per 4,096-value item (tables of up to 16 requests in the kernel's
+ * arguments); larger, the persistent grid with 256 values per lane, at most
+ * 8 waves per compute unit, fitted to the batch.
  * Errors: RNGX_E_BUSY if already running; RNGX_E_INVAL (n_states == 0, NULL
  * or misaligned pool, pool_bytes < 256, n_streams outside 1..16,
  * max_batch == 0); RNGX_E_NOMEM; RNGX_E_HIP. */
@@ -341,7 +346,8 @@ int rngx_serve_start(uint64_t seed, uint32_t n_states, void *pool, uint64_t pool
  * rngx_serve_submit waits while the pending bound (rngx_serve_set_max_pending)
  * is reached; rngx_serve_try_submit returns RNGX_E_BUSY instead.
  * Errors: RNGX_E_NOINIT (not running); RNGX_E_INVAL (NULL ticket, stream out
- * of range, length 0 or above the pool, unknown flags); RNGX_E_BUSY. */
+ * of range, length 0 or above the pool, unknown flags, a cursor that would
+ * pass value number 2^64 - 1); RNGX_E_BUSY. */
 int rngx_serve_submit(uint32_t stream_id, uint64_t length, uint32_t flags, uint64_t *ticket);
 int rngx_serve_try_submit(uint32_t stream_id, uint64_t length, uint32_t flags,
                           uint64_t *ticket);

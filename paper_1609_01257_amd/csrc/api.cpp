@@ -128,6 +128,8 @@ int generate_locked(Generator &c, uint32_t n_iters, void *out, hipStream_t s, bo
     const unsigned __int128 bytes = (unsigned __int128)n_iters * c.n * esize;
     if (bytes > (unsigned __int128)SIZE_MAX)
         return set_error(RNGX_E_INVAL, "generate: output size overflows size_t");
+    if (c.cursor > UINT64_MAX - n_iters)
+        return set_error(RNGX_E_INVAL, "generate: the cursor would pass value number 2^64 - 1");
     int rc = check_device_locked(c);
     if (rc)
         return rc;

@@ -242,6 +242,9 @@ int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out
     for (uint32_t j = 0; j < m; ++j) {
         if (reqs[j].reserved)
             return set_error(RNGX_E_INVAL, "batch: request %u has a nonzero reserved field", j);
+        if (reqs[j].length && reqs[j].offset > UINT64_MAX - (reqs[j].length - 1))
+            return set_error(RNGX_E_INVAL,
+                             "batch: request %u runs past value number 2^64 - 1", j);
         total += reqs[j].length;
     }
     if (total > (unsigned __int128)UINT64_MAX / 8)

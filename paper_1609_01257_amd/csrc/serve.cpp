@@ -214,6 +214,10 @@ int launch_admitted(Server &s, Flight &f, std::vector<StageReq> &items, const Se
         f.busy = true;
         ++s.batches;
         s.batch_reqs += items.size();
+    } else {
+        // The batch never ran: its requests must never be reported done.
+        // The caller records the failure, which every waiter then receives.
+        f.tickets.clear();
     }
     return rc;
 }
@@ -248,6 +252,7 @@ void worker_main(Server *sp)
             } else if (q != hipErrorNotReady) {
                 s.worker_rc = hip_fail(q, "serve: batch completion");
                 s.worker_msg = rngx_last_error();
+                f.tickets.clear();
                 f.busy = false;
             } else {
                 busy = true;
@@ -257,7 +262,8 @@ void worker_main(Server *sp)
         // in flight still write into the pool, so they are waited for.
         if (!s.stopping)
             progress |= admit(s);
-        while (!s.stopping && !s.admitted.empty()) {
+        // After a failure nothing more is launched; waiters get the error.
+        while (!s.stopping && !s.worker_rc && !s.admitted.empty()) {
             uint32_t inflight = 0;
             for (const Flight &f : s.flights)
                 inflight += f.busy;
@@ -383,6 +389,9 @@ int check_request_locked(Server &s, uint32_t stream_id, uint64_t length, uint32_
                          (unsigned long long)length);
     if (flags & ~(uint32_t)RNGX_SERVE_AUTORELEASE)
         return set_error(RNGX_E_INVAL, "serve: unknown flags 0x%x", flags);
+    if (s.cursor[stream_id] > UINT64_MAX - length)
+        return set_error(RNGX_E_INVAL, "serve: stream %u would pass value number 2^64 - 1",
+                         stream_id);
     if (s.worker_rc)
         return set_error(s.worker_rc, "serve: scheduler failed: %s", s.worker_msg.c_str());
     return RNGX_OK;

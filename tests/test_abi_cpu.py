@@ -172,6 +172,10 @@ def test_batch_argument_errors_without_gpu():
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, None, 3, None) == rngx.RNGX_E_INVAL
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, None, 4, None) == rngx.RNGX_E_INVAL
     assert L.rngx_generate_batch(reqs.ctypes.data, 1, 8, 4, None) == rngx.RNGX_E_INVAL  # misaligned
+    # Value numbers end at 2^64 - 1: offset + length may be 2^64, not more.
+    late = rngx.make_reqs([1], [0], [2**64 - 5], [6])
+    assert L.rngx_generate_batch(late.ctypes.data, 1, 16, 6, None) == rngx.RNGX_E_INVAL
+    assert "2^64 - 1" in rngx.last_error()
     for bad in [(100, 4, 0, 1, 16, 1, 0), (256, 5, 0, 1, 16, 1, 0), (256, 4, 70000, 1, 16, 1, 0),
                 (256, 4, 0, 2, 16, 1, 0), (256, 4, 0, 1, 12, 1, 0), (256, 4, 0, 1, 16, 65, 0),
                 (256, 4, 0, 1, 16, 1, 2)]:

@@ -206,3 +206,19 @@ def test_batched_config_full_size_sampled(oracle):
     assert rngx.checksum(out, r.total) == c1
     del out
     torch.cuda.empty_cache()
+
+
+def test_last_value_numbers_of_a_stream(oracle):
+    # A request may end exactly at value number 2^64 - 1; checked through the
+    # group law (value k+1 = one step from value k) from a host-side jump.
+    r = rngx.make_reqs([5, 5], [3, 4], [2**64 - 6, 2**64 - 1], [6, 1])
+    got = _run(r, 7)
+    for j, (off, n, base) in enumerate([(2**64 - 6, 6, 0), (2**64 - 1, 1, 6)]):
+        x = rngx.jump_ahead(oracle.init_state(5, 3 + j), off)
+        for t in range(n):
+            assert int(got[base + t]) == x, (j, t)
+            x = oracle.rng_step(x)
+    L = rngx.lib()
+    out = torch.zeros(8, dtype=torch.int64, device="cuda")
+    late = rngx.make_reqs([5], [3], [2**64 - 5], [6])
+    assert L.rngx_generate_batch(late.ctypes.data, 1, out.data_ptr(), 8, None) == rngx.RNGX_E_INVAL

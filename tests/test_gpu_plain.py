@@ -301,3 +301,14 @@ def test_scrambler_switch_keeps_the_state_sequence(oracle):
     assert np.array_equal(_u64(b).reshape(3, n), oracle.generate_star(seed, n, 3, cursor=2))
     st, _, c = rngx.get_state()
     assert c == 5 and np.array_equal(st, oracle.generate(seed, n, 1, cursor=5).ravel())
+
+
+def test_cursor_may_not_pass_the_last_value_number(oracle):
+    # The cursor (the next value number) stays at most 2^64 - 1.
+    st = oracle.generate(1, 4, 1).ravel()
+    rngx.set_state(1, st, 2**64 - 4)
+    out = torch.empty(4 * 4, dtype=torch.int64, device="cuda")
+    assert rngx.lib().rngx_generate(4, out.data_ptr(), None) == rngx.RNGX_E_INVAL
+    rngx.generate(3, out)
+    assert rngx.info()[2] == 2**64 - 1
+    assert rngx.lib().rngx_generate(1, out.data_ptr(), None) == rngx.RNGX_E_INVAL
