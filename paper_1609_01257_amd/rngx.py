@@ -299,7 +299,7 @@ def stream_to_host(n_steps: int, iters_per_step: int, dev0, dev1, host, host_slo
                                      cb, None, gs, cs))
 
 
-def set_copy_mode(mode: int, blocks: int = 512):
+def set_copy_mode(mode: int, blocks: int = 16):
     _check(lib().rngx_set_copy_mode(mode, blocks))
 
 
