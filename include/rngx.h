@@ -142,8 +142,10 @@ typedef struct rngx_launch {
 int rngx_set_launch(int u32, const rngx_launch *cfg);
 int rngx_get_launch(int u32, rngx_launch *cfg);
 
-/* Output scrambler of the plain path (rngx_generate, rngx_generate_u32 and
- * rngx_stream_to_host; process-wide, kept across rngx_init). The paper
+/* Output scrambler (process-wide, kept across rngx_init): it applies to
+ * rngx_generate, rngx_generate_u32, rngx_stream_to_host,
+ * rngx_generate_batch and rngx_autotune_batch at each call, and to a
+ * request server as set when rngx_serve_start ran. The paper
  * notes, discussing Fig. 5, that its generator kernels are much shorter
  * than the transfers, so a more complex generator would cost nothing.
  * RNGX_SCRAMBLE_NONE (default): the paper's generator, the state is the
@@ -151,7 +153,7 @@ int rngx_get_launch(int u32, rngx_launch *cfg);
  * RNGX_SCRAMBLE_STAR: the xorshift* construction (Vigna, 2016) on the same
  *   states: each output is the state times 2685821657736338717 modulo 2^64
  *   (its high half for 32-bit output). The states, the cursor, seeding,
- *   checkpoints and the batched and served paths are unchanged.
+ *   checkpoints, jump-ahead and the served cursors are unchanged.
  * Errors: RNGX_E_INVAL for an unknown scrambler or a NULL pointer. */
 #define RNGX_SCRAMBLE_NONE 0
 #define RNGX_SCRAMBLE_STAR 1

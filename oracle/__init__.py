@@ -64,6 +64,8 @@ def lib():
         L.oracle_generate_u32.restype = u64
         L.oracle_scramble.argtypes = [u64]
         L.oracle_scramble.restype = u64
+        L.oracle_scramble_n.argtypes = [p, u64, p]
+        L.oracle_scramble_n.restype = None
         L.oracle_generate_star.argtypes = [u64, u32, u64, u32, p]
         L.oracle_generate_star.restype = u64
         L.oracle_generate_star_u32.argtypes = [u64, u32, u64, u32, p]
@@ -133,6 +135,14 @@ def generate_u32(seed: int, n: int, n_iters: int, cursor: int = 0) -> np.ndarray
 def scramble(x: int) -> int:
     """The scrambled variant's output word for state x (xorshift* reading)."""
     return lib().oracle_scramble(x)
+
+
+def scramble_array(values: np.ndarray) -> np.ndarray:
+    """The scrambled words of an array of uint64 values."""
+    a = np.ascontiguousarray(values, dtype=np.uint64)
+    out = np.empty_like(a)
+    lib().oracle_scramble_n(_ptr(a), a.size, _ptr(out))
+    return out
 
 
 def generate_star(seed: int, n: int, n_iters: int, cursor: int = 0) -> np.ndarray:

@@ -203,6 +203,14 @@ uint64_t oracle_scramble(uint64_t x)
     return x * 2685821657736338717ull;
 }
 
+/* The scrambled words of n given values (for the batched and served forms:
+ * their scrambled output is the scrambled plain output, value by value). */
+void oracle_scramble_n(const uint64_t *in, uint64_t n, uint64_t *out)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = oracle_scramble(in[i]);
+}
+
 uint64_t oracle_generate_star(uint64_t seed, uint32_t n, uint64_t cursor,
                               uint32_t n_iters, uint64_t *out)
 {

@@ -296,6 +296,17 @@ int rngx_set_launch(int u32, const rngx_launch *cfg)
     return RNGX_OK;
 }
 
+} // extern "C"
+
+int rngx::current_scrambler()
+{
+    Generator &c = generator();
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    return c.scrambler;
+}
+
+extern "C" {
+
 int rngx_set_scrambler(int scrambler)
 {
     Generator &c = generator();

@@ -281,7 +281,7 @@ int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out
                              nullptr);
 }
 
-int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stream,
+int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, bool star, hipStream_t stream,
                  bool fit_grid, const char *prof_name)
 {
     const uint64_t *pow2 = nullptr, *spread_all = nullptr, *nib_all = nullptr;
@@ -315,7 +315,7 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
                           slot.exec_cfg.blocks == cfg.blocks &&
                           slot.exec_cfg.row_values == cfg.row_values &&
                           slot.exec_cfg.run_items == cfg.run_items &&
-                          slot.exec_cfg.per_item == cfg.per_item;
+                          slot.exec_cfg.per_item == cfg.per_item && slot.exec_star == star;
         if (!same) {
             if (slot.exec) {
                 (void)hipGraphExecDestroy(slot.exec);
@@ -327,7 +327,7 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
             RNGX_HIP(hipStreamBeginCapture(slot.cap_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e1 = hipMemcpyAsync(slot.devtab, slot.staging, bytes,
                                            hipMemcpyHostToDevice, slot.cap_stream);
-            hipError_t e2 = launch_batch(cfg, ddesc, tabs, slot.cap_stream);
+            hipError_t e2 = launch_batch(cfg, ddesc, tabs, star, slot.cap_stream);
             hipGraph_t graph = nullptr;
             hipError_t e3 = hipStreamEndCapture(slot.cap_stream, &graph);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
@@ -343,6 +343,7 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
                 return hip_fail(e4, "hipGraphInstantiate (batch)");
             }
             slot.exec_cfg = cfg;
+            slot.exec_star = star;
         }
         RNGX_HIP(hipGraphLaunch(slot.exec, stream));
     } else if (cfg.per_item && slot.m_staged <= kSmallReqs) {
@@ -351,13 +352,13 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, hipStream_t stre
         std::memcpy(&st.desc, slot.staging, sizeof(BatchDesc));
         std::memcpy(st.reqs, static_cast<const char *>(slot.staging) + sizeof(BatchDesc),
                     (size_t)slot.m_staged * sizeof(BatchReq));
-        hipError_t e = launch_batch_small(cfg, st, tabs, stream);
+        hipError_t e = launch_batch_small(cfg, st, tabs, star, stream);
         if (e != hipSuccess)
             return hip_fail(e, "batch kernel launch");
     } else {
         const size_t bytes = sizeof(BatchDesc) + (size_t)slot.m_staged * sizeof(BatchReq);
         RNGX_HIP(hipMemcpyAsync(slot.devtab, slot.staging, bytes, hipMemcpyHostToDevice, stream));
-        hipError_t e = launch_batch(cfg, ddesc, tabs, stream);
+        hipError_t e = launch_batch(cfg, ddesc, tabs, star, stream);
         if (e != hipSuccess)
             return hip_fail(e, "batch kernel launch");
     }
@@ -417,7 +418,8 @@ extern "C" int rngx_generate_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
         return rc;
     if (total == 0)
         return RNGX_OK;
-    return batch_launch(g.api_slot, g.cfg, static_cast<hipStream_t>(stream));
+    return batch_launch(g.api_slot, g.cfg, current_scrambler() == RNGX_SCRAMBLE_STAR,
+                        static_cast<hipStream_t>(stream));
 }
 
 extern "C" int rngx_set_batch_cfg(const rngx_batch_cfg *cfg)
@@ -473,6 +475,7 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
     if (rc)
         return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool star = current_scrambler() == RNGX_SCRAMBLE_STAR;
     std::memset(result, 0, sizeof *result);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     RNGX_HIP(hipEventCreate(&e0));
@@ -522,7 +525,7 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
                     return rc;
                 if (total == 0)
                     return set_error(RNGX_E_INVAL, "rngx_autotune_batch: no values requested");
-                rc = batch_launch(g.api_slot, c, s); // warm-up (and graph capture)
+                rc = batch_launch(g.api_slot, c, star, s); // warm-up (and graph capture)
                 if (rc)
                     return rc;
                 uint64_t sum = 0;
@@ -540,7 +543,7 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
                 }
                 RNGX_HIP(hipEventRecord(e0, s));
                 for (uint32_t r = 0; r < reps; ++r) {
-                    rc = batch_launch(g.api_slot, c, s);
+                    rc = batch_launch(g.api_slot, c, star, s);
                     if (rc)
                         return rc;
                 }

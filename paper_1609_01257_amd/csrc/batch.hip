@@ -135,6 +135,14 @@ __device__ __forceinline__ uint64_t lane_carry(const uint64_t *__restrict__ tab,
     return y;
 }
 
+// The word emitted for state x: the state (the paper's generator) or, for the
+// scrambled variant, the state times 2685821657736338717 modulo 2^64 (the
+// xorshift* multiplier of Vigna, 2016).
+template <bool STAR> __device__ __forceinline__ uint64_t out_word(uint64_t x)
+{
+    return STAR ? x * 2685821657736338717ull : x;
+}
+
 // The fields of a request that one work item needs, read once per item.
 struct ItemReq {
     uint64_t offset, length, vbase, item_begin, first_tile;
@@ -164,7 +172,7 @@ __device__ __forceinline__ ItemReq load_req(g_req *__restrict__ reqs, uint32_t j
 // previous tile of the same request), then S values per lane through LDS
 // rows and out with whole-line stores. Returns whether the tile was full,
 // in which case each lane's state ends S values past its start.
-template <int S, int R>
+template <int S, int R, bool STAR>
 __device__ __forceinline__ bool process_item(const ItemReq &r, uint64_t item, bool carry,
                                              uint64_t &x, uint64_t *lds,
                                              const uint64_t *carry_tab,
@@ -232,7 +240,7 @@ __device__ __forceinline__ bool process_item(const ItemReq &r, uint64_t item, bo
         if (full) {
 #pragma unroll
             for (int s = 0; s < ROUND; ++s) {
-                lds[lane * LDS_ROW + s] = x;
+                lds[lane * LDS_ROW + s] = out_word<STAR>(x);
                 x = xs_step(x);
             }
         } else {
@@ -240,7 +248,7 @@ __device__ __forceinline__ bool process_item(const ItemReq &r, uint64_t item, bo
             for (int s = 0; s < ROUND; ++s) {
                 const uint64_t P = p0 + s;
                 if (P >= B && P < E) {
-                    lds[lane * LDS_ROW + s] = x;
+                    lds[lane * LDS_ROW + s] = out_word<STAR>(x);
                     x = xs_step(x);
                 }
             }
@@ -290,7 +298,7 @@ __device__ __forceinline__ bool process_item(const ItemReq &r, uint64_t item, bo
     return full;
 }
 
-template <int S, int R>
+template <int S, int R, bool STAR>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict__ desc,
                                                     const uint64_t *__restrict__ pow2,
                                                     const uint64_t *__restrict__ spread,
@@ -361,8 +369,8 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
             req_end = lo + 1 < m ? (uint64_t)reqs[lo + 1].item_begin : n_items;
         }
         const ItemReq r = load_req(reqs, lo);
-        const bool full = process_item<S, R>(r, item, carry, x, lds, carry_tab, pow2, spread,
-                                             states, lane);
+        const bool full = process_item<S, R, STAR>(r, item, carry, x, lds, carry_tab, pow2,
+                                                   spread, states, lane);
         // Lane l now holds the state at T0 + l*S + S when the tile was full.
         ++item;
         carry = full && item < run_end && item < req_end;
@@ -371,7 +379,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
 
 // A batch of at most kSmallReqs requests with its table in the kernel's
 // arguments: one wave per work item, no table upload before the launch.
-template <int S, int R>
+template <int S, int R, bool STAR>
 __global__ __launch_bounds__(256) void batch_small_kernel(const SmallTable t,
                                                           const uint64_t *__restrict__ pow2,
                                                           const uint64_t *__restrict__ spread)
@@ -402,11 +410,11 @@ __global__ __launch_bounds__(256) void batch_small_kernel(const SmallTable t,
     r.mix_high = q.mix_high;
     r.zero_fix = q.zero_fix;
     uint64_t x = 0;
-    (void)process_item<S, R>(r, item, false, x, lds, nullptr, pow2, spread,
-                             (g_cu64 *)t.desc.states, lane);
+    (void)process_item<S, R, STAR>(r, item, false, x, lds, nullptr, pow2, spread,
+                                   (g_cu64 *)t.desc.states, lane);
 }
 
-template <int S>
+template <int S, bool STAR>
 hipError_t launch_batch_s(const BatchDesc *desc, const BatchTables &t, const rngx_batch_cfg &c,
                           hipStream_t s)
 {
@@ -414,25 +422,25 @@ hipError_t launch_batch_s(const BatchDesc *desc, const BatchTables &t, const rng
         (kCarryTable + (size_t)c.waves_per_block * 64 * lds_row(c.row_values)) * sizeof(uint64_t);
     const uint32_t run = c.run_items ? c.run_items : 1;
     if (c.row_values == 8)
-        batch_kernel<S, 8><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
+        batch_kernel<S, 8, STAR><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
             desc, t.pow2, t.spread, t.carry_nib, run, c.per_item);
     else
-        batch_kernel<S, 16><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
+        batch_kernel<S, 16, STAR><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
             desc, t.pow2, t.spread, t.carry_nib, run, c.per_item);
     return hipGetLastError();
 }
 
-template <int S>
+template <int S, bool STAR>
 hipError_t launch_batch_small_s(const SmallTable &tab, const BatchTables &t,
                                 const rngx_batch_cfg &c, hipStream_t s)
 {
     const size_t lds_bytes = (size_t)c.waves_per_block * 64 * lds_row(c.row_values) * 8;
     if (c.row_values == 8)
-        batch_small_kernel<S, 8><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
-            tab, t.pow2, t.spread);
+        batch_small_kernel<S, 8, STAR>
+            <<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(tab, t.pow2, t.spread);
     else
-        batch_small_kernel<S, 16><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
-            tab, t.pow2, t.spread);
+        batch_small_kernel<S, 16, STAR>
+            <<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(tab, t.pow2, t.spread);
     return hipGetLastError();
 }
 
@@ -474,32 +482,48 @@ bool batch_cfg_valid(const rngx_batch_cfg &c)
            c.run_items <= 64 && c.per_item <= 1;
 }
 
-hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const BatchTables &t,
-                        hipStream_t s)
+template <bool STAR>
+hipError_t launch_batch_star(const rngx_batch_cfg &cfg, const BatchDesc *desc,
+                             const BatchTables &t, hipStream_t s)
 {
     switch (cfg.values_per_lane) {
-    case 16: return launch_batch_s<16>(desc, t, cfg, s);
-    case 32: return launch_batch_s<32>(desc, t, cfg, s);
-    case 64: return launch_batch_s<64>(desc, t, cfg, s);
-    case 128: return launch_batch_s<128>(desc, t, cfg, s);
-    case 256: return launch_batch_s<256>(desc, t, cfg, s);
-    case 512: return launch_batch_s<512>(desc, t, cfg, s);
-    default: return launch_batch_s<1024>(desc, t, cfg, s);
+    case 16: return launch_batch_s<16, STAR>(desc, t, cfg, s);
+    case 32: return launch_batch_s<32, STAR>(desc, t, cfg, s);
+    case 64: return launch_batch_s<64, STAR>(desc, t, cfg, s);
+    case 128: return launch_batch_s<128, STAR>(desc, t, cfg, s);
+    case 256: return launch_batch_s<256, STAR>(desc, t, cfg, s);
+    case 512: return launch_batch_s<512, STAR>(desc, t, cfg, s);
+    default: return launch_batch_s<1024, STAR>(desc, t, cfg, s);
     }
 }
 
-hipError_t launch_batch_small(const rngx_batch_cfg &cfg, const SmallTable &tab,
-                              const BatchTables &t, hipStream_t s)
+template <bool STAR>
+hipError_t launch_batch_small_star(const rngx_batch_cfg &cfg, const SmallTable &tab,
+                                   const BatchTables &t, hipStream_t s)
 {
     switch (cfg.values_per_lane) {
-    case 16: return launch_batch_small_s<16>(tab, t, cfg, s);
-    case 32: return launch_batch_small_s<32>(tab, t, cfg, s);
-    case 64: return launch_batch_small_s<64>(tab, t, cfg, s);
-    case 128: return launch_batch_small_s<128>(tab, t, cfg, s);
-    case 256: return launch_batch_small_s<256>(tab, t, cfg, s);
-    case 512: return launch_batch_small_s<512>(tab, t, cfg, s);
-    default: return launch_batch_small_s<1024>(tab, t, cfg, s);
+    case 16: return launch_batch_small_s<16, STAR>(tab, t, cfg, s);
+    case 32: return launch_batch_small_s<32, STAR>(tab, t, cfg, s);
+    case 64: return launch_batch_small_s<64, STAR>(tab, t, cfg, s);
+    case 128: return launch_batch_small_s<128, STAR>(tab, t, cfg, s);
+    case 256: return launch_batch_small_s<256, STAR>(tab, t, cfg, s);
+    case 512: return launch_batch_small_s<512, STAR>(tab, t, cfg, s);
+    default: return launch_batch_small_s<1024, STAR>(tab, t, cfg, s);
     }
+}
+
+hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const BatchTables &t,
+                        bool star, hipStream_t s)
+{
+    return star ? launch_batch_star<true>(cfg, desc, t, s)
+                : launch_batch_star<false>(cfg, desc, t, s);
+}
+
+hipError_t launch_batch_small(const rngx_batch_cfg &cfg, const SmallTable &tab,
+                              const BatchTables &t, bool star, hipStream_t s)
+{
+    return star ? launch_batch_small_star<true>(cfg, tab, t, s)
+                : launch_batch_small_star<false>(cfg, tab, t, s);
 }
 
 } // namespace rngx

@@ -134,6 +134,7 @@ struct BatchSlot {
     hipEvent_t done = nullptr; // recorded after the slot's last launch
     hipGraphExec_t exec = nullptr;
     rngx_batch_cfg exec_cfg{};
+    bool exec_star = false;
     hipStream_t cap_stream = nullptr;
     uint32_t m_staged = 0;
     uint64_t n_items = 0;
@@ -168,17 +169,20 @@ struct StageReq {
 };
 int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
                       uint32_t values_per_lane, const uint64_t *states);
-// fit_grid: shrink the persistent grid to the staged work (direct launches).
-int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg, hipStream_t stream,
+// star: emit the scrambled words. fit_grid: shrink the persistent grid to the
+// staged work (direct launches).
+int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg, bool star, hipStream_t stream,
                  bool fit_grid = false, const char *prof_name = "BATCH_KERNEL");
+// The output scrambler set by rngx_set_scrambler (api.cpp; thread-safe).
+int current_scrambler();
 void release_slot(BatchSlot &slot);
 void release_batch();
 void release_server(); // serve.cpp: stop the server, free its resources
 int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *result);
 hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const BatchTables &t,
-                        hipStream_t s);
+                        bool star, hipStream_t s);
 hipError_t launch_batch_small(const rngx_batch_cfg &cfg, const SmallTable &tab,
-                              const BatchTables &t, hipStream_t s);
+                              const BatchTables &t, bool star, hipStream_t s);
 // Checksum sum_i data[i] * (2 i + 1) mod 2^64 into *acc (device, pre-zeroed).
 hipError_t launch_checksum(const uint64_t *data, uint64_t n, uint64_t *acc, hipStream_t s);
 

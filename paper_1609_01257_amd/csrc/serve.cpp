@@ -95,6 +95,7 @@ struct Server {
     uint32_t max_batch = 1024;
     uint64_t max_pending = 1u << 20;
     uint32_t max_inflight = 3;
+    bool star = false; // the output scrambler, fixed at start
     rngx_batch_cfg cfg{256, 4, 0, 0, 16, 1, 0};
     std::thread worker;
     int worker_rc = RNGX_OK;
@@ -206,7 +207,7 @@ int launch_admitted(Server &s, Flight &f, std::vector<StageReq> &items, const Se
     int rc = batch_stage_items(f.slot, items.data(), (uint32_t)items.size(), cfg.values_per_lane,
                                s.d_states);
     if (rc == RNGX_OK)
-        rc = batch_launch(f.slot, cfg, f.stream, true, "SERVE_KERNEL");
+        rc = batch_launch(f.slot, cfg, s.star, f.stream, true, "SERVE_KERNEL");
     const uint64_t t = now_ns();
     for (uint64_t tk : f.tickets)
         s.reqs.find(tk)->t_launch = t;
@@ -587,6 +588,7 @@ extern "C" int rngx_serve_start(uint64_t seed, uint32_t n_states, void *pool, ui
     // items, 4 waves per block, 8 waves per CU at most; S and the schedule
     // are chosen per batch.
     s.cfg = rngx_batch_cfg{256, 4, 0, 0, 16, 1, 0};
+    s.star = current_scrambler() == RNGX_SCRAMBLE_STAR;
     s.worker_rc = RNGX_OK;
     s.worker_msg.clear();
     reset_stats_locked(s);

@@ -67,7 +67,7 @@ def test_every_per_item_config(oracle, S, wpb, graph, row):
 def test_small_tables_in_kernel_arguments(oracle, m, S):
     # Up to 16 requests, one wave per item and no graph: the request table
     # travels in the kernel's arguments (17 takes the uploaded-table path).
-    r = inputs.ragged_requests(m=m, seed=500 + m, max_len=90000, max_offset=10**7)
+    r = inputs.ragged_requests(m=m, seed=500 + m, max_len=90000, max_offset=10**6)
     exp = oracle.generate_batch(_oracle_reqs(oracle, r))
     for row in (8, 16):
         rngx.set_batch_cfg(S, 4, 0, False, row, 1, True)
@@ -222,3 +222,23 @@ def test_last_value_numbers_of_a_stream(oracle):
     out = torch.zeros(8, dtype=torch.int64, device="cuda")
     late = rngx.make_reqs([5], [3], [2**64 - 5], [6])
     assert L.rngx_generate_batch(late.ctypes.data, 1, out.data_ptr(), 8, None) == rngx.RNGX_E_INVAL
+
+
+@pytest.mark.parametrize("S,per_item,graph,m", [(256, False, True, 23), (64, True, False, 23),
+                                                (64, True, False, 9), (128, True, True, 23),
+                                                (32, False, False, 23)])
+def test_scrambled_batches_match_oracle(oracle, S, per_item, graph, m):
+    # The scrambler applies to batched output: each value's scrambled word.
+    r = inputs.ragged_requests(m=m, seed=77 + m, max_len=200000, max_offset=10**6)
+    exp = oracle.scramble_array(oracle.generate_batch(_oracle_reqs(oracle, r)))
+    rngx.set_batch_cfg(S, 4, 0 if per_item else 37, graph, 16, 1 if per_item else 3, per_item)
+    rngx.set_scrambler(rngx.SCRAMBLE_STAR)
+    try:
+        got = _run(_reqs(r), r.total)
+        # Switching back gives the plain words again (a captured graph too).
+        rngx.set_scrambler(rngx.SCRAMBLE_NONE)
+        plain = _run(_reqs(r), r.total)
+    finally:
+        rngx.set_scrambler(rngx.SCRAMBLE_NONE)
+    assert np.array_equal(got, exp)
+    assert np.array_equal(plain, oracle.generate_batch(_oracle_reqs(oracle, r)))

@@ -212,3 +212,21 @@ def test_inflight_cap_keeps_results(oracle, server, max_inflight):
         rngx.serve_release(int(t))
     st = rngx.serve_stats()
     assert st["completed"] == len(hist) and st["batches"] >= len(hist) // 32
+
+
+def test_scrambled_server_matches_oracle(oracle, server):
+    # A server started with the scrambler on serves scrambled words; the
+    # cursor rule is unchanged.
+    seed = 808
+    rngx.set_scrambler(rngx.SCRAMBLE_STAR)
+    try:
+        pool = server(seed, 300, 256 << 20)
+    finally:
+        rngx.set_scrambler(rngx.SCRAMBLE_NONE)
+    hist = _history(11, 150, 300, 40000) + [(7, 3000000)]   # one batch above 2^20 values
+    tickets = [rngx.serve_submit(g, L) for g, L in hist]
+    exp = oracle.serve_expected(seed, hist)
+    for t, (g, L), e in zip(tickets, hist, exp):
+        got = _values(pool, rngx.serve_wait(t, 60.0), L)
+        assert np.array_equal(got, oracle.scramble_array(e)), (g, L)
+        rngx.serve_release(t)
