@@ -6,6 +6,7 @@
 // streams: a generate call makes its stream wait for `state_ready`,
 // launches, and re-records it.
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -135,8 +136,9 @@ int generate_locked(Generator &c, uint32_t n_iters, void *out, hipStream_t s, bo
         return rc;
     RNGX_HIP(hipStreamWaitEvent(s, c.state_ready, 0));
     const int tok = prof::begin("RNG_KERNEL", s);
-    hipError_t e = launch_gen(u32 ? c.cfg32 : c.cfg64, u32, c.scrambler == RNGX_SCRAMBLE_STAR,
-                              c.state, c.n, n_iters, out, s);
+    hipError_t e = launch_gen(u32 ? c.cfg32 : c.cfg64, u32,
+                              current_scrambler() == RNGX_SCRAMBLE_STAR, c.state, c.n, n_iters,
+                              out, s);
     prof::end(tok, s);
     if (e != hipSuccess)
         return hip_fail(e, "rng kernel launch");
@@ -298,34 +300,29 @@ int rngx_set_launch(int u32, const rngx_launch *cfg)
 
 } // extern "C"
 
-int rngx::current_scrambler()
-{
-    Generator &c = generator();
-    std::lock_guard<std::recursive_mutex> lk(c.mu);
-    return c.scrambler;
-}
+// The scrambler is read by the batched and served paths while they hold
+// their own locks; an atomic keeps it out of every lock order.
+static std::atomic<int> g_scrambler{RNGX_SCRAMBLE_NONE};
+
+int rngx::current_scrambler() { return g_scrambler.load(std::memory_order_acquire); }
 
 extern "C" {
 
 int rngx_set_scrambler(int scrambler)
 {
-    Generator &c = generator();
-    std::lock_guard<std::recursive_mutex> lk(c.mu);
     clear_error();
     if (scrambler != RNGX_SCRAMBLE_NONE && scrambler != RNGX_SCRAMBLE_STAR)
         return set_error(RNGX_E_INVAL, "rngx_set_scrambler: unknown scrambler %d", scrambler);
-    c.scrambler = scrambler;
+    g_scrambler.store(scrambler, std::memory_order_release);
     return RNGX_OK;
 }
 
 int rngx_get_scrambler(int *scrambler)
 {
-    Generator &c = generator();
-    std::lock_guard<std::recursive_mutex> lk(c.mu);
     clear_error();
     if (!scrambler)
         return set_error(RNGX_E_INVAL, "rngx_get_scrambler: NULL");
-    *scrambler = c.scrambler;
+    *scrambler = current_scrambler();
     return RNGX_OK;
 }
 

@@ -173,7 +173,7 @@ int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
 // staged work (direct launches).
 int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg, bool star, hipStream_t stream,
                  bool fit_grid = false, const char *prof_name = "BATCH_KERNEL");
-// The output scrambler set by rngx_set_scrambler (api.cpp; thread-safe).
+// The output scrambler set by rngx_set_scrambler (api.cpp; lock-free read).
 int current_scrambler();
 void release_slot(BatchSlot &slot);
 void release_batch();
@@ -218,7 +218,6 @@ struct Generator {
     hipEvent_t gen_done[2] = {nullptr, nullptr};
     hipEvent_t copy_done[2] = {nullptr, nullptr};
     int copy_mode = RNGX_COPY_KERNEL;
-    int scrambler = RNGX_SCRAMBLE_NONE; // output word of the plain path
     // 16 workgroups saturate PCIe 5.0 x16 on MI355X and slow the overlapping
     // generation kernel least (measured: 16 to 256 all within 4 %).
     uint32_t copy_blocks = 16;
