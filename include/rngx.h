@@ -125,11 +125,16 @@ const char *rngx_strerror(int code);
 /* Launch configuration of the plain generator                               */
 /* ------------------------------------------------------------------------ */
 
-/* block: threads per block (64..1024, a multiple of 64).
+/* block: threads per block (64..1024, a multiple of 64), or 0 for the
+ *        library's choice by n_states at each call (the other fields are
+ *        then ignored).
  * chunks: 16-byte stores per lane per iteration (1, 2 or 4); a lane then
  *         owns 2*chunks (u64) or 4*chunks (u32) work-items, and every store
  *         instruction of a wavefront covers 1 KiB of contiguous output.
  * nontemporal: 1 to use non-temporal (streaming) stores.
+ * Defaults: u64 block 512, 4 chunks, normal stores; u32 the library's
+ * choice (measured on MI355X: block 256 with 4 chunks up to 2^20 states,
+ * block 512 with 4 chunks below 2^26, block 512 with 2 chunks from 2^26).
  * The output never depends on the configuration. */
 typedef struct rngx_launch {
     uint32_t block;

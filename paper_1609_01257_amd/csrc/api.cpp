@@ -136,7 +136,16 @@ int generate_locked(Generator &c, uint32_t n_iters, void *out, hipStream_t s, bo
         return rc;
     RNGX_HIP(hipStreamWaitEvent(s, c.state_ready, 0));
     const int tok = prof::begin("RNG_KERNEL", s);
-    hipError_t e = launch_gen(u32 ? c.cfg32 : c.cfg64, u32,
+    rngx_launch cfg = u32 ? c.cfg32 : c.cfg64;
+    if (cfg.block == 0) {
+        // The library's choice by size (u32 launches measured on MI355X:
+        // more work-items per lane pays below 2^26 states, fewer lanes
+        // per block up to 2^20).
+        cfg.block = c.n <= (1u << 20) ? 256 : 512;
+        cfg.chunks = c.n < (1u << 26) ? 4 : (u32 ? 2 : 4);
+        cfg.nontemporal = 0;
+    }
+    hipError_t e = launch_gen(cfg, u32,
                               current_scrambler() == RNGX_SCRAMBLE_STAR, c.state, c.n, n_iters,
                               out, s);
     prof::end(tok, s);
@@ -290,10 +299,10 @@ int rngx_set_launch(int u32, const rngx_launch *cfg)
     Generator &c = generator();
     std::lock_guard<std::recursive_mutex> lk(c.mu);
     clear_error();
-    if (!cfg || !launch_cfg_valid(*cfg))
+    if (!cfg || (cfg->block != 0 && !launch_cfg_valid(*cfg)))
         return set_error(RNGX_E_INVAL,
-                         "rngx_set_launch: block must be 64..1024 in steps of 64, chunks 1, 2 "
-                         "or 4, nontemporal 0 or 1");
+                         "rngx_set_launch: block must be 0 (automatic) or 64..1024 in steps of "
+                         "64, chunks 1, 2 or 4, nontemporal 0 or 1");
     (u32 ? c.cfg32 : c.cfg64) = *cfg;
     return RNGX_OK;
 }

@@ -212,7 +212,7 @@ struct Generator {
     hipStream_t lib_stream = nullptr; // the init kernel's stream
     hipEvent_t state_ready = nullptr; // last use of `state` (any stream)
     rngx_launch cfg64{512, 4, 0}; // fastest measured at 2^26 x 256 on MI355X
-    rngx_launch cfg32{512, 2, 0};
+    rngx_launch cfg32{0, 0, 0};      // chosen per call by n (auto_launch_u32)
     // Streams and events of the device-to-host pipeline (pipeline.cpp).
     hipStream_t pipe_gen = nullptr, pipe_copy = nullptr;
     hipEvent_t gen_done[2] = {nullptr, nullptr};

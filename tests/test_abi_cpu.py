@@ -82,7 +82,14 @@ def test_set_launch_validation():
         assert rngx.lib().rngx_set_launch(0, ctypes.byref(cfg)) == rngx.RNGX_E_INVAL
     rngx.set_launch(False, 512, 4, True)
     assert rngx.get_launch(False) == {"block": 512, "chunks": 4, "nontemporal": True}
-    rngx.set_launch(False, 256, 2, False)
+    rngx.set_launch(False, 512, 4, False)
+    # u32 defaults to the library's choice by size (block 0); it can be set
+    # explicitly and back.
+    assert rngx.get_launch(True)["block"] == 0
+    rngx.set_launch(True, 256, 1, False)
+    assert rngx.get_launch(True) == {"block": 256, "chunks": 1, "nontemporal": False}
+    rngx.set_launch(True, 0, 0, False)
+    assert rngx.get_launch(True)["block"] == 0
 
 
 def _cmp(lib_stats, orc):

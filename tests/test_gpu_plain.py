@@ -69,6 +69,20 @@ def test_zero_iterations_is_noop(oracle):
 
 
 @pytest.mark.parametrize("u32", [False, True])
+@pytest.mark.parametrize("n", [1000, (1 << 20) + 3, (1 << 22) + 6])
+def test_automatic_launch_choice(oracle, u32, n):
+    # block 0: the library picks the configuration by n; same output.
+    default = rngx.get_launch(u32)
+    try:
+        rngx.set_launch(u32, 0, 0, False)
+        got = run(8, n, 2, u32=u32, offset=1)
+        exp = (oracle.generate_u32 if u32 else oracle.generate)(8, n, 2)
+        assert np.array_equal(got, exp)
+    finally:
+        rngx.set_launch(u32, default["block"], default["chunks"], default["nontemporal"])
+
+
+@pytest.mark.parametrize("u32", [False, True])
 def test_every_launch_config_gives_identical_output(oracle, u32):
     n, iters, seed = 100003, 5, 77
     exp = (oracle.generate_u32 if u32 else oracle.generate)(seed, n, iters)
