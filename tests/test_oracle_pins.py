@@ -344,3 +344,20 @@ def test_bit_frequency(oracle):
     s_obs = abs(2 * total - nbits) / math.sqrt(nbits)
     p = math.erfc(s_obs / math.sqrt(2))
     assert p >= 0.01, p
+
+
+def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    # Every oracle function, edge sizes included, in a sanitized build: no
+    # out-of-bounds access, leak-free allocation paths, no undefined shifts
+    # or overflows of signed types.
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = str(tmp_path / "oracle_sanity")
+    subprocess.run(["gcc", "-std=c99", "-O1", "-g", "-Wall", "-Wextra",
+                    "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    os.path.join(root, "oracle", "oracle.c"),
+                    os.path.join(root, "tests", "helpers", "oracle_sanity.c"), "-o", exe],
+                   check=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
