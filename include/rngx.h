@@ -400,8 +400,9 @@ int rngx_serve_reset_stats(void);
 
 /* Open-loop load driver: submit request i (stream_id[i], length[i], with
  * RNGX_SERVE_AUTORELEASE) at arrival_s[i] seconds after the call starts
- * (arrival_s non-decreasing; every request already due is submitted in one
- * call of rngx_serve_submit_many, so equal arrival times form a backlog),
+ * (arrival_s non-decreasing; the requests already due are submitted together,
+ * by rngx_serve_submit_many in chunks of at most 512, so equal arrival times
+ * form a backlog),
  * then wait until every request has completed
  * (at most timeout_s) and report the statistics of this trace (they are
  * reset at the start). Errors: as rngx_serve_submit; RNGX_E_BUSY on timeout. */

@@ -72,7 +72,9 @@ int fresh_state_locked(Generator &c, uint32_t n_states, const char *who)
     int dev = -1;
     RNGX_HIP(hipGetDevice(&dev));
     if (c.lib_stream && dev != c.device) {
-        // Resources belong to another device: recreate them here.
+        // Resources belong to another device: recreate them here (the
+        // streaming pipeline's streams and events on first use).
+        release_pipeline_locked(c);
         (void)hipStreamDestroy(c.lib_stream);
         (void)hipEventDestroy(c.state_ready);
         c.lib_stream = nullptr;

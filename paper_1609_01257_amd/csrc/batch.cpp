@@ -32,15 +32,22 @@ int s_index(uint32_t s)
     return -1;
 }
 
+// Device tables, one set per device that has launched a batch; kept until
+// rngx_shutdown, so work in flight on one device never loses its tables when
+// another device becomes current.
+struct DevTables {
+    int n_cus = 0;
+    uint64_t *d_pow2 = nullptr;      // 64 matrices x 64 rows
+    uint64_t *d_spread = nullptr;    // lane-spread tables for each allowed S (kNumS x kSpreadTable)
+    uint64_t *d_carry_nib = nullptr; // T^(63 S) nibble tables for each allowed S (kNumS x 256)
+    uint64_t *d_acc = nullptr;       // checksum accumulator
+    uint64_t *h_acc = nullptr;       // page-locked copy of it
+};
+constexpr int kMaxDevices = 64;
+
 struct BatchGlobals {
     std::mutex mu;
-    int device = -1;
-    int n_cus = 0;
-    uint64_t *d_pow2 = nullptr;   // 64 matrices x 64 rows
-    uint64_t *d_spread = nullptr;     // lane-spread tables for each allowed S (kNumS x kSpreadTable)
-    uint64_t *d_carry_nib = nullptr; // T^(63 S) nibble tables for each allowed S (kNumS x 256)
-    uint64_t *d_acc = nullptr;    // checksum accumulator
-    uint64_t *h_acc = nullptr;    // page-locked copy of it
+    DevTables dev[kMaxDevices];
     rngx_batch_cfg cfg{256, 4, 0, 1, 16, 1, 0};
     BatchSlot api_slot;
 };
@@ -49,6 +56,66 @@ BatchGlobals &G()
 {
     static BatchGlobals *g = new BatchGlobals;
     return *g;
+}
+
+void free_tables(DevTables &t)
+{
+    if (t.d_pow2)
+        (void)hipFree(t.d_pow2);
+    if (t.d_spread)
+        (void)hipFree(t.d_spread);
+    if (t.d_carry_nib)
+        (void)hipFree(t.d_carry_nib);
+    if (t.d_acc)
+        (void)hipFree(t.d_acc);
+    if (t.h_acc)
+        (void)hipHostFree(t.h_acc);
+    t = DevTables();
+}
+
+// Host images of the lane-spread and carry tables for every allowed S.
+void build_host_tables(std::vector<uint64_t> &spread, std::vector<uint64_t> &nib)
+{
+    spread.assign((size_t)kNumS * kSpreadTable, 0);
+    nib.assign((size_t)kNumS * kCarryTable, 0);
+    for (int i = 0; i < kNumS; ++i) {
+        const uint64_t S = kValuesPerLane[i];
+        // Lane spread: entry ((16 q + v) * 64 + m) is T^(m S) (v << 4q),
+        // so a lane m places above a wave-uniform state z with the XOR of
+        // one entry per nibble of z.
+        uint64_t *sp = spread.data() + (size_t)kSpreadTable * i;
+        for (uint32_t m = 0; m < 64; ++m) {
+            uint64_t rows[64], col[64] = {0};
+            power_rows(m * S, rows);
+            for (int r = 0; r < 64; ++r)
+                for (int j = 0; j < 64; ++j)
+                    col[j] |= ((rows[r] >> j) & 1u) << r;
+            for (int q = 0; q < 16; ++q)
+                for (int v = 0; v < 16; ++v) {
+                    uint64_t e = 0;
+                    for (int b = 0; b < 4; ++b)
+                        if ((v >> b) & 1)
+                            e ^= col[4 * q + b];
+                    sp[(16 * q + v) * 64 + m] = e;
+                }
+        }
+        // A lane that just emitted its S values of a tile is C - S = 63 S
+        // values short of its start in the next tile. M = T^(63 S) is
+        // stored as 16 tables of 16 entries: entry v of table q is
+        // M (v << 4q), so M x is the XOR of 16 lookups, one per nibble.
+        uint64_t carry_rows[64];
+        power_rows(63ull * S, carry_rows);
+        uint64_t col[64] = {0};
+        for (int r = 0; r < 64; ++r)
+            for (int j = 0; j < 64; ++j)
+                col[j] |= ((carry_rows[r] >> j) & 1u) << r;
+        uint64_t *t = nib.data() + (size_t)kCarryTable * i;
+        for (int q = 0; q < 16; ++q)
+            for (int v = 0; v < 16; ++v)
+                for (int b = 0; b < 4; ++b)
+                    if ((v >> b) & 1)
+                        t[16 * q + v] ^= col[4 * q + b];
+    }
 }
 
 void free_slot(BatchSlot &s)
@@ -79,80 +146,48 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **spread_all, int 
     BatchGlobals &g = G();
     int dev = -1;
     RNGX_HIP(hipGetDevice(&dev));
-    if (g.device != dev || !g.d_pow2) {
-        if (g.d_pow2)
-            (void)hipFree(g.d_pow2);
-        if (g.d_spread)
-            (void)hipFree(g.d_spread);
-        if (g.d_carry_nib)
-            (void)hipFree(g.d_carry_nib);
-        if (g.d_acc)
-            (void)hipFree(g.d_acc);
-        if (g.h_acc)
-            (void)hipHostFree(g.h_acc);
-        g.d_pow2 = g.d_spread = g.d_carry_nib = g.d_acc = g.h_acc = nullptr;
-        std::vector<uint64_t> spread((size_t)kNumS * kSpreadTable, 0),
-            nib(kNumS * kCarryTable, 0);
-        for (int i = 0; i < kNumS; ++i) {
-            const uint64_t S = kValuesPerLane[i];
-            // Lane spread: entry ((16 q + v) * 64 + m) is T^(m S) (v << 4q),
-            // so a lane m places above a wave-uniform state z with the XOR of
-            // one entry per nibble of z.
-            uint64_t *sp = spread.data() + (size_t)kSpreadTable * i;
-            for (uint32_t m = 0; m < 64; ++m) {
-                uint64_t rows[64], col[64] = {0};
-                power_rows(m * S, rows);
-                for (int r = 0; r < 64; ++r)
-                    for (int j = 0; j < 64; ++j)
-                        col[j] |= ((rows[r] >> j) & 1u) << r;
-                for (int q = 0; q < 16; ++q)
-                    for (int v = 0; v < 16; ++v) {
-                        uint64_t e = 0;
-                        for (int b = 0; b < 4; ++b)
-                            if ((v >> b) & 1)
-                                e ^= col[4 * q + b];
-                        sp[(16 * q + v) * 64 + m] = e;
-                    }
-            }
-            // A lane that just emitted its S values of a tile is C - S = 63 S
-            // values short of its start in the next tile. M = T^(63 S) is
-            // stored as 16 tables of 16 entries: entry v of table q is
-            // M (v << 4q), so M x is the XOR of 16 lookups, one per nibble.
-            uint64_t carry_rows[64];
-            power_rows(63ull * S, carry_rows);
-            uint64_t col[64] = {0};
-            for (int r = 0; r < 64; ++r)
-                for (int j = 0; j < 64; ++j)
-                    col[j] |= ((carry_rows[r] >> j) & 1u) << r;
-            uint64_t *t = nib.data() + kCarryTable * i;
-            for (int q = 0; q < 16; ++q)
-                for (int v = 0; v < 16; ++v)
-                    for (int b = 0; b < 4; ++b)
-                        if ((v >> b) & 1)
-                            t[16 * q + v] ^= col[4 * q + b];
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(RNGX_E_INVAL, "batch: device %d is beyond the %d the library supports",
+                         dev, kMaxDevices);
+    DevTables &t = g.dev[dev];
+    if (!t.d_pow2) {
+        std::vector<uint64_t> spread, nib;
+        build_host_tables(spread, nib);
+        DevTables n;
+        hipError_t e = hipMalloc(&n.d_pow2, 64 * 64 * sizeof(uint64_t));
+        if (e == hipSuccess)
+            e = hipMalloc(&n.d_spread, spread.size() * sizeof(uint64_t));
+        if (e == hipSuccess)
+            e = hipMalloc(&n.d_carry_nib, nib.size() * sizeof(uint64_t));
+        if (e == hipSuccess)
+            e = hipMalloc(&n.d_acc, sizeof(uint64_t));
+        if (e == hipSuccess)
+            e = hipHostMalloc(&n.h_acc, sizeof(uint64_t), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipMemcpy(n.d_pow2, jump_tables(), 64 * 64 * sizeof(uint64_t),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(n.d_spread, spread.data(), spread.size() * sizeof(uint64_t),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(n.d_carry_nib, nib.data(), nib.size() * sizeof(uint64_t),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&n.n_cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) {
+            free_tables(n);
+            return hip_fail(e, "batch: device tables");
         }
-        RNGX_HIP(hipMalloc(&g.d_pow2, 64 * 64 * sizeof(uint64_t)));
-        RNGX_HIP(hipMalloc(&g.d_spread, spread.size() * sizeof(uint64_t)));
-        RNGX_HIP(hipMalloc(&g.d_carry_nib, nib.size() * sizeof(uint64_t)));
-        RNGX_HIP(hipMalloc(&g.d_acc, sizeof(uint64_t)));
-        RNGX_HIP(hipHostMalloc(&g.h_acc, sizeof(uint64_t), hipHostMallocDefault));
-        RNGX_HIP(hipMemcpy(g.d_pow2, jump_tables(), 64 * 64 * sizeof(uint64_t),
-                           hipMemcpyHostToDevice));
-        RNGX_HIP(hipMemcpy(g.d_spread, spread.data(), spread.size() * sizeof(uint64_t),
-                           hipMemcpyHostToDevice));
-        RNGX_HIP(hipMemcpy(g.d_carry_nib, nib.data(), nib.size() * sizeof(uint64_t),
-                           hipMemcpyHostToDevice));
-        RNGX_HIP(hipDeviceGetAttribute(&g.n_cus, hipDeviceAttributeMultiprocessorCount, dev));
-        g.device = dev;
+        t = n;
     }
     if (pow2)
-        *pow2 = g.d_pow2;
+        *pow2 = t.d_pow2;
     if (spread_all)
-        *spread_all = g.d_spread;
+        *spread_all = t.d_spread;
     if (carry_nib_all)
-        *carry_nib_all = g.d_carry_nib;
+        *carry_nib_all = t.d_carry_nib;
     if (n_cus)
-        *n_cus = g.n_cus;
+        *n_cus = t.n_cus;
     return RNGX_OK;
 }
 
@@ -167,6 +202,14 @@ rngx_batch_cfg resolved_cfg(const rngx_batch_cfg &c, int n_cus)
 int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
                       uint32_t values_per_lane, const uint64_t *states)
 {
+    // A slot's buffers, event and graph belong to the device they were made
+    // on; when another device is current, the slot starts over there.
+    int dev = -1;
+    RNGX_HIP(hipGetDevice(&dev));
+    if (slot.device != dev) {
+        free_slot(slot);
+        slot.device = dev;
+    }
     // Grow the slot to a power-of-two capacity (>= 64 requests).
     if (k > slot.capacity || !slot.staging) {
         uint32_t cap = 64;
@@ -374,18 +417,16 @@ void release_batch()
     BatchGlobals &g = G();
     std::lock_guard<std::mutex> lk(g.mu);
     free_slot(g.api_slot);
-    if (g.d_pow2)
-        (void)hipFree(g.d_pow2);
-    if (g.d_spread)
-        (void)hipFree(g.d_spread);
-    if (g.d_carry_nib)
-        (void)hipFree(g.d_carry_nib);
-    if (g.d_acc)
-        (void)hipFree(g.d_acc);
-    if (g.h_acc)
-        (void)hipHostFree(g.h_acc);
-    g.d_pow2 = g.d_spread = g.d_carry_nib = g.d_acc = g.h_acc = nullptr;
-    g.device = -1;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    for (int d = 0; d < kMaxDevices; ++d) {
+        if (!g.dev[d].d_pow2)
+            continue;
+        (void)hipSetDevice(d);
+        free_tables(g.dev[d]);
+    }
+    if (cur >= 0)
+        (void)hipSetDevice(cur);
 }
 
 int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *result)
@@ -393,12 +434,14 @@ int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *r
     int rc = batch_tables_locked(nullptr, nullptr, nullptr);
     if (rc)
         return rc;
-    BatchGlobals &g = G();
-    RNGX_HIP(hipMemsetAsync(g.d_acc, 0, sizeof(uint64_t), s));
-    RNGX_HIP(launch_checksum(data, n, g.d_acc, s));
-    RNGX_HIP(hipMemcpyAsync(g.h_acc, g.d_acc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    int dev = -1;
+    RNGX_HIP(hipGetDevice(&dev));
+    DevTables &t = G().dev[dev];
+    RNGX_HIP(hipMemsetAsync(t.d_acc, 0, sizeof(uint64_t), s));
+    RNGX_HIP(launch_checksum(data, n, t.d_acc, s));
+    RNGX_HIP(hipMemcpyAsync(t.h_acc, t.d_acc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     RNGX_HIP(hipStreamSynchronize(s));
-    *result = *g.h_acc;
+    *result = *t.h_acc;
     return RNGX_OK;
 }
 
@@ -428,10 +471,10 @@ extern "C" int rngx_set_batch_cfg(const rngx_batch_cfg *cfg)
     std::lock_guard<std::mutex> lk(g.mu);
     clear_error();
     if (!cfg || !batch_cfg_valid(*cfg))
-        return set_error(RNGX_E_INVAL, "rngx_set_batch_cfg: values_per_lane must be 64, 128, "
-                                       "256, 512 or 1024, waves_per_block 1..4, blocks "
-                                       "0..65536 (0 = 16 waves per compute unit), use_graph 0/1, "
-                                       "row_values 8 or 16, run_items 0..64");
+        return set_error(RNGX_E_INVAL, "rngx_set_batch_cfg: values_per_lane must be 16, 32, 64, "
+                                       "128, 256, 512 or 1024, waves_per_block 1..4, blocks "
+                                       "0..65536 (0 = 8 waves per compute unit), use_graph 0/1, "
+                                       "row_values 8 or 16, run_items 0..64, per_item 0/1");
     g.cfg = *cfg;
     return RNGX_OK;
 }

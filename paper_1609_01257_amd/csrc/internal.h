@@ -128,6 +128,7 @@ struct SmallTable {
 
 // A staging/upload slot for one batch in flight (batch.cpp).
 struct BatchSlot {
+    int device = -1;          // the device its buffers, event and graph are on
     uint32_t capacity = 0;    // requests the buffers hold (power of two)
     void *staging = nullptr;  // page-locked: BatchDesc + capacity BatchReq
     void *devtab = nullptr;   // device copy of the same

@@ -312,8 +312,11 @@ void worker_main(Server *sp)
                 while (s.submit_seq.load(std::memory_order_acquire) == seq && now_ns() < until)
                     __builtin_ia32_pause();
                 lk.lock();
+                // Nothing can move until a submission or a release (both wake
+                // this thread): no requests, or the pool is full of results
+                // that their consumers still hold.
                 if (s.submit_seq.load(std::memory_order_acquire) == seq && !s.stopping &&
-                    s.pending.empty() && s.admitted.empty())
+                    (s.pending.empty() || s.stalled) && s.admitted.empty())
                     s.cv_work.wait_for(lk, std::chrono::milliseconds(5));
             }
         }
@@ -398,6 +401,13 @@ int check_request_locked(Server &s, uint32_t stream_id, uint64_t length, uint32_
     return RNGX_OK;
 }
 
+// Tell the scheduler that requests were queued (or memory freed).
+void wake_worker(Server &s)
+{
+    s.submit_seq.fetch_add(1, std::memory_order_release);
+    s.cv_work.notify_one();
+}
+
 // Wait (or fail with BUSY) until one more request may be pending.
 int make_room_locked(Server &s, std::unique_lock<std::mutex> &lk, bool wait)
 {
@@ -405,6 +415,9 @@ int make_room_locked(Server &s, std::unique_lock<std::mutex> &lk, bool wait)
         if (!wait)
             return set_error(RNGX_E_BUSY, "serve: %llu requests already pending",
                              (unsigned long long)s.pending.size());
+        // The pending requests (some perhaps queued by this very caller) are
+        // what must move for room to appear.
+        wake_worker(s);
         s.cv_done.wait(lk);
         if (!s.active || s.stopping)
             return set_error(RNGX_E_NOINIT, "serve: the server stopped");
@@ -448,8 +461,7 @@ int submit_impl(uint32_t stream_id, uint64_t length, uint32_t flags, uint64_t *t
     if (rc)
         return rc;
     *ticket = enqueue_locked(s, stream_id, length, flags);
-    s.submit_seq.fetch_add(1, std::memory_order_release);
-    s.cv_work.notify_one();
+    wake_worker(s);
     return RNGX_OK;
 }
 
@@ -459,19 +471,22 @@ int submit_many_impl(const uint32_t *ids, const uint64_t *lengths, uint64_t k, u
 {
     Server &s = SV();
     std::unique_lock<std::mutex> lk(s.mu);
-    for (uint64_t i = 0; i < k; ++i) {
-        int rc = check_request_locked(s, ids[i], lengths[i], flags);
+    int rc = RNGX_OK;
+    uint64_t i = 0;
+    for (; i < k; ++i) {
+        rc = check_request_locked(s, ids[i], lengths[i], flags);
         if (rc == RNGX_OK)
             rc = make_room_locked(s, lk, true);
         if (rc)
-            return rc;
+            break;
         const uint64_t tk = enqueue_locked(s, ids[i], lengths[i], flags);
         if (tickets)
             tickets[i] = tk;
     }
-    s.submit_seq.fetch_add(1, std::memory_order_release);
-    s.cv_work.notify_one();
-    return RNGX_OK;
+    // The requests queued before a failure stand, so they are scheduled too.
+    if (i > 0)
+        wake_worker(s);
+    return rc;
 }
 
 void stop_locked(Server &s, std::unique_lock<std::mutex> &lk)
@@ -683,8 +698,7 @@ extern "C" int rngx_serve_release(uint64_t ticket)
     s.alloc.release(rp->pool_seq);
     ++s.released;
     s.reqs.erase(ticket);
-    s.submit_seq.fetch_add(1, std::memory_order_release);
-    s.cv_work.notify_one(); // memory freed: admission may proceed
+    wake_worker(s); // memory freed: admission may proceed
     return RNGX_OK;
 }
 

@@ -73,6 +73,11 @@ def test_submit_many_matches_single_submissions(oracle, server):
         rngx.serve_submit_many([1, 2, 50, 3], [10, 10, 10, 10])
     st = rngx.serve_stats()
     assert st["submitted"] == len(hist) + 2
+    # ... and are scheduled without a further submission.
+    deadline = time.time() + 30.0
+    while rngx.serve_stats()["completed"] < len(hist) + 2:
+        assert time.time() < deadline
+        time.sleep(0.001)
 
 
 def test_alone_and_in_the_mix_are_identical(oracle, server):
