@@ -290,6 +290,8 @@ def main():
                     help="run only the serving runs (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 16 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--placement-probe", action="store_true",
+                    help="only time one launch shape into three separately allocated buffers")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -310,6 +312,33 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log("copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
+        return
+    if args.placement_probe:
+        # One launch shape (u32, 2^26 states x 256 iterations, 64 GiB of
+        # output) into three buffers from separate allocations: the write
+        # rate of the row-ordered store stream depends on where a buffer
+        # landed in HBM, reproducibly per buffer.
+        n, iters = 1 << 26, 256
+        rngx.init(1, n)
+        bufs = [torch.empty(n * iters, dtype=torch.int32, device="cuda") for _ in range(3)]
+        res = []
+        st = torch.cuda.current_stream()
+        for i, buf in enumerate(bufs):
+            rngx.generate_u32(iters, buf)
+            torch.cuda.synchronize()
+            rates = []
+            for _ in range(3):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(st)
+                rngx.generate_u32(iters, buf)
+                b.record(st)
+                b.synchronize()
+                rates.append(round(n * iters * 4 / (a.elapsed_time(b) * 1e-3) / 1e9, 1))
+            log("placement probe: buffer %d at 0x%x: %s GB/s" % (i, buf.data_ptr(), rates))
+            res.append({"buffer": i, "kernel_gbs": rates})
+        rngx.shutdown()
+        print(json.dumps({"placement_probe": res}), flush=True)
         return
     if args.batched_only:
         rngx.init(1, 64)          # opens the profiling window the step is timed in
