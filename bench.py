@@ -57,10 +57,12 @@ def kernel_avg_s(stats, name):
     raise RuntimeError("no %s events were profiled" % name)
 
 
-def plain_run(torch, rngx, seed, n, iters, u32, warmup, steps):
-    """Time `steps` generate calls of `iters` iterations over n streams."""
+def plain_run(torch, rngx, seed, n, iters, u32, warmup, steps, out=None):
+    """Time `steps` generate calls of `iters` iterations over n streams
+    (into `out` if given, else into a new buffer)."""
     rngx.init(seed, n)
-    out = torch.empty(n * iters, dtype=torch.int32 if u32 else torch.int64, device="cuda")
+    if out is None:
+        out = torch.empty(n * iters, dtype=torch.int32 if u32 else torch.int64, device="cuda")
     gen = rngx.generate_u32 if u32 else rngx.generate
     for _ in range(warmup):
         gen(iters, out)
@@ -243,6 +245,16 @@ def serving(torch, rngx, seconds, plain_gbs):
                              "admission_stalls": st["admission_stalls"],
                              "p99_us": round(st["lat_p99_us"], 1)}
         res["saturation"]["served_vs_plain"] = round(st["gbs"] / plain_gbs, 4)
+        rngx.serve_stop()
+        # The plain kernel writing the pool itself (2^22 states x 476
+        # iterations = 15.97 GB per launch): the same memory the served
+        # batches wrote, so the ratio does not depend on where either
+        # buffer landed in HBM.
+        n_pool, it_pool = 1 << 22, 476
+        pp = plain_run(torch, rngx, 1, n_pool, it_pool, False, 1, 5,
+                       out=pool.view(torch.int64)[: n_pool * it_pool])
+        res["saturation"]["plain_in_pool_gbs"] = round(pp["kernel_gbs"], 1)
+        res["saturation"]["served_vs_plain_in_pool"] = round(st["gbs"] / pp["kernel_gbs"], 4)
         log("serving saturation:", res["saturation"])
     finally:
         rngx.serve_stop()
