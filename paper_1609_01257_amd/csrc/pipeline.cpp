@@ -157,6 +157,13 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
     }
     void *dev[2] = {dev0, dev1};
     char *hbase = static_cast<char *>(host);
+    // On an error or an abort, wait for everything already enqueued on both
+    // streams, so that no kernel or copy still uses the caller's buffers
+    // when the call returns.
+    auto drain = [&]() {
+        (void)hipStreamSynchronize(gs);
+        (void)hipStreamSynchronize(cs);
+    };
 
     auto consume_step = [&](uint64_t k) -> int {
         const uint32_t slot = (uint32_t)(k % host_slots);
@@ -174,7 +181,7 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
         if (consume && k >= host_slots) {
             rc = consume_step(k - host_slots);
             if (rc) {
-                (void)hipStreamSynchronize(cs);
+                drain();
                 return rc;
             }
         }
@@ -182,7 +189,7 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
             RNGX_HIP(hipStreamWaitEvent(gs, g.copy_done[b], 0));
         rc = generate_locked(g, iters_per_step, dev[b], gs, u32 != 0);
         if (rc) {
-            (void)hipStreamSynchronize(cs);
+            drain();
             return rc;
         }
         RNGX_HIP(hipEventRecord(g.gen_done[b], gs));
@@ -195,7 +202,7 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
                                             hipMemcpyDeviceToHost, cs);
         prof::end(tok, cs);
         if (e != hipSuccess) {
-            (void)hipStreamSynchronize(cs);
+            drain();
             return hip_fail(e, hmapped ? "device-to-host copy kernel" : "hipMemcpyAsync (D2H)");
         }
         RNGX_HIP(hipEventRecord(g.copy_done[b], cs));
@@ -207,7 +214,7 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
         for (uint64_t k = first; k < n_steps; ++k) {
             rc = consume_step(k);
             if (rc) {
-                (void)hipStreamSynchronize(cs);
+                drain();
                 return rc;
             }
         }

@@ -272,7 +272,8 @@ def stream_to_host(n_steps: int, iters_per_step: int, dev0, dev1, host, host_slo
     tensor of host_slots slots) through device buffers dev0/dev1, generation
     and copies overlapped on two streams. `consume(step, array)` (optional)
     receives each step as a numpy view of its host slot, in order; returning
-    a true value stops the stream (raises RngxError with RNGX_E_ABORTED)."""
+    a true value stops the stream (raises RngxError with RNGX_E_ABORTED), and
+    an exception it raises stops the stream and is re-raised here."""
     import numpy as np
     n = info()[1]
     esize = 4 if u32 else 8
@@ -285,18 +286,26 @@ def stream_to_host(n_steps: int, iters_per_step: int, dev0, dev1, host, host_slo
         raise ValueError("host holds %d elements, %d needed" % (host.numel(), step_elems * host_slots))
     dev_bytes = min(dev0.numel(), dev1.numel()) * esize
     cb = CONSUME_FN()
+    raised = []
     if consume is not None:
         npdt = np.uint32 if u32 else np.uint64
 
         def _cb(user, step, ptr, nbytes):
-            arr = np.ctypeslib.as_array((ctypes.c_uint8 * nbytes).from_address(ptr)).view(npdt)
-            return 1 if consume(step, arr) else 0
+            try:
+                arr = np.ctypeslib.as_array((ctypes.c_uint8 * nbytes).from_address(ptr)).view(npdt)
+                return 1 if consume(step, arr) else 0
+            except BaseException as e:  # stop the stream; re-raised below
+                raised.append(e)
+                return 1
         cb = CONSUME_FN(_cb)
     gs = stream_handle(gen_stream) if gen_stream is not None else 0
     cs = stream_handle(copy_stream) if copy_stream is not None else 0
-    _check(lib().rngx_stream_to_host(n_steps, iters_per_step, int(u32), dev0.data_ptr(),
-                                     dev1.data_ptr(), dev_bytes, host.data_ptr(), host_slots,
-                                     cb, None, gs, cs))
+    rc = lib().rngx_stream_to_host(n_steps, iters_per_step, int(u32), dev0.data_ptr(),
+                                   dev1.data_ptr(), dev_bytes, host.data_ptr(), host_slots,
+                                   cb, None, gs, cs)
+    if raised:
+        raise raised[0]
+    _check(rc)
 
 
 def set_copy_mode(mode: int, blocks: int = 16):

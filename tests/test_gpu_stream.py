@@ -89,6 +89,27 @@ def test_consumer_abort_stops_and_reports(oracle):
     assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle.generate(seed, n, 1, cursor=c)[0])
 
 
+def test_consumer_exception_stops_and_propagates(oracle):
+    seed, n = 4, 2048
+    rngx.init(seed, n)
+    dev0, dev1, host = _buffers(n, 1, 2)
+    seen = []
+
+    def consume(step, arr):
+        seen.append(step)
+        if step == 2:
+            raise KeyError("consumer failed at step 2")
+    with pytest.raises(KeyError):
+        rngx.stream_to_host(20, 1, dev0, dev1, host, 2, consume=consume)
+    assert seen == [0, 1, 2]
+    # The library is usable afterwards and continues the cursor.
+    c = rngx.info()[2]
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    rngx.generate(1, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle.generate(seed, n, 1, cursor=c)[0])
+
+
 def test_pageable_host_memory_uses_runtime_copy(oracle):
     # Ordinary (not page-locked) host memory cannot be written by the copy
     # kernel; the pipeline must still deliver every value.
