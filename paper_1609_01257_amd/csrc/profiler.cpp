@@ -87,7 +87,9 @@ static int analyze_rows(const std::vector<EventRow> &rows, const std::vector<std
     out->n_events = rows.size();
     out->total_s = total * 1e-9;
     out->overlap_s = overlap * 1e-9;
-    out->eff_s = (double)(total - overlap) * 1e-9;
+    // Signed: with three or more queues the pairwise overlaps can add up to
+    // more than the total, and the formula then goes negative.
+    out->eff_s = ((double)total - (double)overlap) * 1e-9;
     out->elapsed_s = elapsed_s;
     if (elapsed_s > 0) {
         out->device_pct = 100.0 * out->eff_s / elapsed_s;
@@ -190,10 +192,14 @@ static std::string format_summary(const rngx_prof_stats &st)
 namespace prof {
 namespace {
 
+// Tokens: window number << 16 | record index (the log holds at most 2^16).
+constexpr size_t kMaxRecs = 1u << 16;
+
 struct Rec {
     uint32_t name;
     hipStream_t stream;
     hipEvent_t ev0, ev1;
+    bool ended; // end() recorded ev1 (an operation that failed to launch never ends)
 };
 
 struct State {
@@ -206,12 +212,16 @@ struct State {
     hipEvent_t ref = nullptr;
     std::chrono::steady_clock::time_point t0, t1;
     uint64_t dropped = 0;
-    size_t cap = 65536;
+    size_t cap = kMaxRecs;
     std::string summary;
     // Resolved rows of the last closed window.
     std::vector<EventRow> rows;
     bool resolved = false;
+    // Window number (low 15 bits), carried in tokens so that an end() for a
+    // record of an earlier window is ignored.
+    uint32_t gen = 0;
 };
+
 
 State &S()
 {
@@ -247,23 +257,40 @@ void recycle(State &st)
     st.recs.clear();
     st.rows.clear();
     st.resolved = false;
+    st.gen = (st.gen + 1) & 0x7fffu;
+}
+
+// Wait until every ended record's end event has completed.
+int sync_ended(State &st)
+{
+    for (Rec &r : st.recs)
+        if (r.ended)
+            RNGX_HIP(hipEventSynchronize(r.ev1));
+    return RNGX_OK;
 }
 
 // Wait for the logged work, stop the clock, resolve events to rows.
 int close_locked(State &st)
 {
     if (st.open) {
-        for (Rec &r : st.recs)
-            RNGX_HIP(hipEventSynchronize(r.ev1));
+        int rc = sync_ended(st);
+        if (rc)
+            return rc;
         st.t1 = std::chrono::steady_clock::now();
         st.open = false;
     }
     if (!st.resolved) {
+        // Records ended after the window closed are resolved too.
+        int rc = sync_ended(st);
+        if (rc)
+            return rc;
         st.rows.clear();
         std::vector<int64_t> starts(st.recs.size());
         std::vector<uint64_t> durs(st.recs.size());
         int64_t lo = 0;
         for (size_t i = 0; i < st.recs.size(); ++i) {
+            if (!st.recs[i].ended)
+                continue;
             float ms0 = 0.f, msd = 0.f;
             RNGX_HIP(hipEventElapsedTime(&ms0, st.ref, st.recs[i].ev0));
             RNGX_HIP(hipEventElapsedTime(&msd, st.recs[i].ev0, st.recs[i].ev1));
@@ -272,6 +299,8 @@ int close_locked(State &st)
             lo = std::min(lo, starts[i]);
         }
         for (size_t i = 0; i < st.recs.size(); ++i) {
+            if (!st.recs[i].ended)
+                continue;
             EventRow row;
             row.name = st.recs[i].name;
             row.queue = (uint64_t)(uintptr_t)st.recs[i].stream;
@@ -299,6 +328,7 @@ int begin(const char *name, hipStream_t s)
     Rec r;
     r.name = name_id(st, name);
     r.stream = s;
+    r.ended = false;
     if (take_event(st, &r.ev0) != hipSuccess)
         return -1;
     if (take_event(st, &r.ev1) != hipSuccess) {
@@ -312,7 +342,7 @@ int begin(const char *name, hipStream_t s)
     }
     st.recs.push_back(r);
     st.resolved = false;
-    return (int)st.recs.size() - 1;
+    return (int)((st.gen << 16) | (uint32_t)(st.recs.size() - 1));
 }
 
 void end(int token, hipStream_t s)
@@ -321,8 +351,13 @@ void end(int token, hipStream_t s)
         return;
     State &st = S();
     std::lock_guard<std::mutex> lk(st.mu);
-    if ((size_t)token < st.recs.size())
-        (void)hipEventRecord(st.recs[token].ev1, s);
+    const uint32_t gen = (uint32_t)token >> 16, idx = (uint32_t)token & 0xffffu;
+    if (gen != st.gen || idx >= st.recs.size() || st.recs[idx].ended)
+        return; // a record of an earlier window
+    if (hipEventRecord(st.recs[idx].ev1, s) == hipSuccess) {
+        st.recs[idx].ended = true;
+        st.resolved = false;
+    }
 }
 
 int start(hipStream_t ref_stream)
@@ -330,8 +365,7 @@ int start(hipStream_t ref_stream)
     State &st = S();
     std::lock_guard<std::mutex> lk(st.mu);
     // Events of the previous window may still be pending; wait before reuse.
-    for (Rec &r : st.recs)
-        (void)hipEventSynchronize(r.ev1);
+    (void)sync_ended(st);
     recycle(st);
     st.dropped = 0;
     if (!st.ref)
@@ -355,8 +389,7 @@ void release_all()
 {
     State &st = S();
     std::lock_guard<std::mutex> lk(st.mu);
-    for (Rec &r : st.recs)
-        (void)hipEventSynchronize(r.ev1);
+    (void)sync_ended(st);
     recycle(st);
     for (hipEvent_t e : st.pool)
         (void)hipEventDestroy(e);

@@ -131,6 +131,17 @@ def test_profile_analyze_random_matches_oracle(seed):
     _cmp(rngx.profile_analyze(rows, 1e-6 * (1 + seed)), oprof.analyze(ev, 1e-6 * (1 + seed)))
 
 
+def test_profile_analyze_overlaps_beyond_total():
+    # Four events of 10 ns in flight together on four queues: the six
+    # pairwise overlaps (60 ns) exceed the total (40 ns), and the printed
+    # formula gives a negative effective time.
+    rows = [("K", q, 0, 10) for q in range(4)]
+    ev = [oprof.Event(n, str(q), s, e) for n, q, s, e in rows]
+    orc = oprof.analyze(ev, 1e-6)
+    assert round(orc.eff_s * 1e9) == -20
+    _cmp(rngx.profile_analyze(rows, 1e-6), orc)
+
+
 def test_profile_analyze_rejects_backwards_event():
     with pytest.raises(rngx.RngxError):
         rngx.profile_analyze([("K", 0, 10, 5)], 1.0)
