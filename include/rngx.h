@@ -478,8 +478,13 @@ typedef struct rngx_prof_stats {
     rngx_prof_overlap overlap[RNGX_PROF_MAX_OVERLAP];
 } rngx_prof_stats;
 
-/* Clear the event log and open a new profiling window (host clock starts). */
+/* Clear the event log and open a new profiling window (host clock starts).
+ * Errors: RNGX_E_NOINIT before rngx_init. */
 int rngx_profile_start(void);
+
+/* The same as rngx_profile_start: the log restarts empty (the name used for
+ * the operation in the library's call list). */
+int rngx_profile_reset(void);
 
 /* Wait for every logged operation to finish and close the window. */
 int rngx_profile_stop(void);

@@ -358,6 +358,8 @@ int rngx_profile_start(void)
     return prof::start(c.lib_stream);
 }
 
+int rngx_profile_reset(void) { return rngx_profile_start(); }
+
 int rngx_profile_stop(void)
 {
     clear_error();

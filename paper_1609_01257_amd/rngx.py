@@ -143,6 +143,7 @@ _SIGS = {
     "rngx_serve_set_max_inflight": ([_u32], _int),
     "rngx_serve_stop": ([], _int),
     "rngx_profile_start": ([], _int),
+    "rngx_profile_reset": ([], _int),
     "rngx_profile_stop": ([], _int),
     "rngx_profile_enable": ([_int], _int),
     "rngx_profile": ([], ctypes.c_char_p),
@@ -515,6 +516,11 @@ def get_launch(u32: bool):
 
 def profile_start():
     _check(lib().rngx_profile_start())
+
+
+def profile_reset():
+    """Same as :func:`profile_start`."""
+    _check(lib().rngx_profile_reset())
 
 
 def profile_stop():

@@ -47,6 +47,14 @@ def test_generate_before_init_is_noinit():
         rngx.info()
 
 
+def test_profile_window_before_init_is_noinit():
+    rngx.shutdown()
+    L = rngx.lib()
+    assert L.rngx_profile_start() == rngx.RNGX_E_NOINIT
+    assert L.rngx_profile_reset() == rngx.RNGX_E_NOINIT
+    assert "before rngx_init" in rngx.last_error()
+
+
 def test_init_zero_states_is_inval():
     assert rngx.lib().rngx_init(0, 0) == rngx.RNGX_E_INVAL
 

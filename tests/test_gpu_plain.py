@@ -160,6 +160,11 @@ def test_profile_records_every_call():
     assert len(ev) == 6 and all(e[3] >= e[2] for e in ev)
     text = rngx.profile()
     assert "RNG_KERNEL" in text and "INIT_KERNEL" in text and "Time spent in device" in text
+    # A reset starts an empty window that logs what follows.
+    rngx.profile_reset()
+    rngx.generate(4, out)
+    st = rngx.profile_stats()
+    assert {name: c for name, c, _, _ in st["agg"]} == {"RNG_KERNEL": 1}
 
 
 def test_abi_errors_on_device():
