@@ -216,7 +216,6 @@ struct Generator {
     rngx_launch cfg32{0, 0, 0};      // chosen per call by n (auto_launch_u32)
     // Streams and events of the device-to-host pipeline (pipeline.cpp).
     hipStream_t pipe_gen = nullptr, pipe_copy = nullptr;
-    hipEvent_t gen_done[2] = {nullptr, nullptr};
     hipEvent_t copy_done[2] = {nullptr, nullptr};
     int copy_mode = RNGX_COPY_KERNEL;
     // 16 workgroups saturate PCIe 5.0 x16 on MI355X and slow the overlapping
@@ -237,6 +236,11 @@ namespace prof {
 int begin(const char *name, hipStream_t s);
 // Close it: records its end event on the same stream.
 void end(int token, hipStream_t s);
+// The same, returning the end event it recorded (nullptr if none): a caller
+// may order other streams after the operation with it instead of recording
+// an event of its own. The event stays valid until the profiling window is
+// restarted, which needs the generator lock.
+hipEvent_t end_event(int token, hipStream_t s);
 // Restart the window (log cleared, host clock and reference event reset).
 int start(hipStream_t ref_stream);
 int stop();

@@ -6,9 +6,11 @@
 // Step k generates `iters_per_step` iterations into device buffer k % 2 on
 // the generation stream and copies it into host slot k % host_slots on the
 // copy stream. HIP events replace the paper's two semaphores:
-//   - the copy of step k waits for `gen_done[k % 2]` (generation k finished);
-//   - generation k waits for `copy_done[k % 2]` (the copy of step k - 2,
-//     which read the same device buffer, finished).
+//   - the copy of step k waits for the generator's own state_ready event,
+//     recorded right after generation k;
+//   - generation k waits for the end of the copy of step k - 2, which read
+//     the same device buffer: the profiler's end event of that copy when it
+//     was profiled, else `copy_done[k % 2]`.
 // Here the output buffers are double-buffered, not the state (the state
 // stays in a library buffer and, inside one launch, in registers), so
 // generation of step k + 1 may run while step k is still being copied.
@@ -29,11 +31,9 @@ void release_pipeline_locked(Generator &g)
     if (g.pipe_gen)
         (void)hipStreamSynchronize(g.pipe_gen);
     for (int i = 0; i < 2; ++i) {
-        if (g.gen_done[i])
-            (void)hipEventDestroy(g.gen_done[i]);
         if (g.copy_done[i])
             (void)hipEventDestroy(g.copy_done[i]);
-        g.gen_done[i] = g.copy_done[i] = nullptr;
+        g.copy_done[i] = nullptr;
     }
     if (g.pipe_gen)
         (void)hipStreamDestroy(g.pipe_gen);
@@ -51,8 +51,6 @@ int ensure_pipeline_locked(Generator &g)
     if (!g.pipe_copy)
         RNGX_HIP(hipStreamCreateWithFlags(&g.pipe_copy, hipStreamNonBlocking));
     for (int i = 0; i < 2; ++i) {
-        if (!g.gen_done[i])
-            RNGX_HIP(hipEventCreateWithFlags(&g.gen_done[i], hipEventDisableTiming));
         if (!g.copy_done[i])
             RNGX_HIP(hipEventCreateWithFlags(&g.copy_done[i], hipEventDisableTiming));
     }
@@ -156,6 +154,7 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
             RNGX_HIP(hipEventCreateWithFlags(&slots.ev[i], hipEventDisableTiming));
     }
     void *dev[2] = {dev0, dev1};
+    hipEvent_t copy_dep[2] = {nullptr, nullptr}; // end of the copy that last read dev[b]
     char *hbase = static_cast<char *>(host);
     // On an error or an abort, wait for everything already enqueued on both
     // streams, so that no kernel or copy still uses the caller's buffers
@@ -186,26 +185,33 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
             }
         }
         if (k >= 2)
-            RNGX_HIP(hipStreamWaitEvent(gs, g.copy_done[b], 0));
+            RNGX_HIP(hipStreamWaitEvent(gs, copy_dep[b], 0));
         rc = generate_locked(g, iters_per_step, dev[b], gs, u32 != 0);
         if (rc) {
             drain();
             return rc;
         }
-        RNGX_HIP(hipEventRecord(g.gen_done[b], gs));
-        RNGX_HIP(hipStreamWaitEvent(cs, g.gen_done[b], 0));
+        // generate_locked recorded state_ready on gs right after the kernel:
+        // it marks the generation's end, so no event of our own is queued.
+        RNGX_HIP(hipStreamWaitEvent(cs, g.state_ready, 0));
         const int tok = prof::begin("READ_BUFFER", cs);
         hipError_t e = hmapped
                            ? launch_d2h(dev[b], hmapped + (size_t)slot * step_bytes, step_bytes,
                                         g.copy_blocks, cs)
                            : hipMemcpyAsync(hbase + (size_t)slot * step_bytes, dev[b], step_bytes,
                                             hipMemcpyDeviceToHost, cs);
-        prof::end(tok, cs);
+        // The profiler's end event of the copy, when there is one, also
+        // orders generation k + 2 after it (one marker fewer per step).
+        hipEvent_t copied = prof::end_event(tok, cs);
         if (e != hipSuccess) {
             drain();
             return hip_fail(e, hmapped ? "device-to-host copy kernel" : "hipMemcpyAsync (D2H)");
         }
-        RNGX_HIP(hipEventRecord(g.copy_done[b], cs));
+        if (!copied) {
+            RNGX_HIP(hipEventRecord(g.copy_done[b], cs));
+            copied = g.copy_done[b];
+        }
+        copy_dep[b] = copied;
         if (consume)
             RNGX_HIP(hipEventRecord(slots.ev[slot], cs));
     }

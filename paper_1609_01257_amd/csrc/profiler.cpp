@@ -345,20 +345,23 @@ int begin(const char *name, hipStream_t s)
     return (int)((st.gen << 16) | (uint32_t)(st.recs.size() - 1));
 }
 
-void end(int token, hipStream_t s)
+hipEvent_t end_event(int token, hipStream_t s)
 {
     if (token < 0)
-        return;
+        return nullptr;
     State &st = S();
     std::lock_guard<std::mutex> lk(st.mu);
     const uint32_t gen = (uint32_t)token >> 16, idx = (uint32_t)token & 0xffffu;
     if (gen != st.gen || idx >= st.recs.size() || st.recs[idx].ended)
-        return; // a record of an earlier window
-    if (hipEventRecord(st.recs[idx].ev1, s) == hipSuccess) {
-        st.recs[idx].ended = true;
-        st.resolved = false;
-    }
+        return nullptr; // a record of an earlier window
+    if (hipEventRecord(st.recs[idx].ev1, s) != hipSuccess)
+        return nullptr;
+    st.recs[idx].ended = true;
+    st.resolved = false;
+    return st.recs[idx].ev1;
 }
+
+void end(int token, hipStream_t s) { (void)end_event(token, s); }
 
 int start(hipStream_t ref_stream)
 {
