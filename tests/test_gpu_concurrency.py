@@ -71,6 +71,48 @@ def test_threads_batching_while_a_server_serves(oracle):
         assert np.array_equal(served[k], e), k
 
 
+def test_threads_submitting_to_shared_streams(oracle):
+    # Four threads submit to the same few streams at once. Each request's
+    # values are fixed when it is submitted (the stream's cursor moves under
+    # the server's lock), and tickets are issued in submission order, so
+    # ordering the submissions by ticket gives the history the oracle needs.
+    seed, n_states = 777, 8
+    pool = torch.zeros(256 << 20, dtype=torch.uint8, device="cuda")
+    rngx.serve_start(seed, n_states, pool, 4, 64)
+    subs, errors = [], []
+    lock = threading.Lock()
+
+    def submitter(t):
+        try:
+            rng = np.random.default_rng(900 + t)
+            for _ in range(60):
+                g, L = int(rng.integers(0, n_states)), int(rng.integers(1, 20000))
+                tk = rngx.serve_submit(g, L)
+                with lock:
+                    subs.append((tk, g, L))
+        except Exception as e:
+            errors.append("submitter %d: %r" % (t, e))
+
+    threads = [threading.Thread(target=submitter, args=(t,)) for t in range(4)]
+    try:
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join(120)
+        assert not any(th.is_alive() for th in threads), "a thread did not finish"
+        assert not errors, errors
+        subs.sort()
+        exp = oracle.serve_expected(seed, [(g, L) for _, g, L in subs])
+        for (tk, g, L), e in zip(subs, exp):
+            ptr = rngx.serve_wait(tk, 30.0)
+            off = ptr - pool.data_ptr()
+            got = pool[off:off + 8 * L].view(torch.int64).cpu().numpy().view(np.uint64)
+            assert np.array_equal(got, e), (tk, g, L)
+            rngx.serve_release(tk)
+    finally:
+        rngx.serve_stop()
+
+
 def test_server_cycles_release_device_memory():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
