@@ -43,7 +43,12 @@ typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 // counter and make every LDS wait stall on outstanding global stores.
 typedef __attribute__((address_space(1))) u64x2 g_u64x2;
 typedef __attribute__((address_space(1))) uint64_t g_u64;
-typedef __attribute__((address_space(1))) const BatchReq g_req;
+// The request table is read-only for the whole launch (it is uploaded
+// before the kernel starts), so it is read through the constant address
+// space: uniform reads (the binary search, a wave's request record) become
+// scalar loads, which wait on the scalar counter instead of the vector one
+// that the wave's outstanding stores also occupy.
+typedef __attribute__((address_space(4))) const BatchReq g_req;
 typedef __attribute__((address_space(1))) const uint64_t g_cu64;
 
 // Each round a lane emits R values (R = 8 or 16: a 64- or 128-byte row of
@@ -108,6 +113,15 @@ __device__ __forceinline__ uint32_t bisect_request(g_req *__restrict__ reqs, uin
             hi = mid;
     }
     return lo;
+}
+
+// A wave-uniform 64-bit value, stated as such to the compiler (its two
+// halves read from the first active lane).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Next work item for the wave: lane 0 bumps the counter with a (vector)
@@ -349,6 +363,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
         run_end = item + 1;
     }
     for (;;) {
+        item = uniform64(item);
         if (item >= run_end) {
             if (per_item)
                 break;
@@ -366,14 +381,20 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
         }
         if (!carry) {
             lo = per_item ? find_request(reqs, m, item, lane) : bisect_request(reqs, m, item);
-            req_end = lo + 1 < m ? (uint64_t)reqs[lo + 1].item_begin : n_items;
+            lo = __builtin_amdgcn_readfirstlane(lo);
+            req_end = uniform64(lo + 1 < m ? (uint64_t)reqs[lo + 1].item_begin : n_items);
         }
         const ItemReq r = load_req(reqs, lo);
         const bool full = process_item<S, R, STAR>(r, item, carry, x, lds, carry_tab, pow2,
                                                    spread, states, lane);
         // Lane l now holds the state at T0 + l*S + S when the tile was full.
+        // Every quantity of this loop is the same in all lanes; saying so
+        // keeps the bookkeeping, the request search and the record loads on
+        // the scalar unit (otherwise the carried flag makes the compiler
+        // treat the next search as divergent, with per-lane vector loads).
         ++item;
-        carry = full && item < run_end && item < req_end;
+        carry = __builtin_amdgcn_readfirstlane(
+                    (uint32_t)(full && item < run_end && item < req_end)) != 0;
     }
 }
 
