@@ -46,6 +46,11 @@ def _compile(src: str, extra) -> str:
 
 def build(extra=(), jobs: int = 8) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
+    # A failed build must not leave the previous library (or program) behind
+    # for the tests to load: remove both before compiling.
+    for stale in (LIB, CLI):
+        if os.path.exists(stale):
+            os.remove(stale)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(srcs)))) as ex:
         objs = list(ex.map(lambda s: _compile(s, list(extra)), srcs))
