@@ -227,7 +227,7 @@ int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
             (void)hipFree(slot.devtab);
         slot.staging = slot.devtab = nullptr;
         slot.capacity = 0;
-        const size_t bytes = sizeof(BatchDesc) + (size_t)cap * sizeof(BatchReq);
+        const size_t bytes = kReqOffset + (size_t)cap * sizeof(BatchReq);
         hipError_t e = hipHostMalloc(&slot.staging, bytes, hipHostMallocDefault);
         if (e != hipSuccess) {
             slot.staging = nullptr;
@@ -248,7 +248,7 @@ int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
 
     const uint64_t C = 64ull * values_per_lane;
     BatchDesc *desc = static_cast<BatchDesc *>(slot.staging);
-    BatchReq *tab = reinterpret_cast<BatchReq *>(desc + 1);
+    BatchReq *tab = reinterpret_cast<BatchReq *>(static_cast<char *>(slot.staging) + kReqOffset);
     uint64_t n_items = 0;
     for (uint32_t j = 0; j < k; ++j) {
         const StageReq &q = items[j];
@@ -267,7 +267,7 @@ int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
     }
     std::memset(desc, 0, sizeof *desc);
     desc->reqs = reinterpret_cast<const BatchReq *>(static_cast<char *>(slot.devtab) +
-                                                    sizeof(BatchDesc));
+                                                    kReqOffset);
     desc->states = states;
     desc->n_items = n_items;
     desc->m = k;
@@ -366,7 +366,7 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, bool star, hipSt
             }
             if (!slot.cap_stream)
                 RNGX_HIP(hipStreamCreateWithFlags(&slot.cap_stream, hipStreamNonBlocking));
-            const size_t bytes = sizeof(BatchDesc) + (size_t)slot.capacity * sizeof(BatchReq);
+            const size_t bytes = kReqOffset + (size_t)slot.capacity * sizeof(BatchReq);
             RNGX_HIP(hipStreamBeginCapture(slot.cap_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e1 = hipMemcpyAsync(slot.devtab, slot.staging, bytes,
                                            hipMemcpyHostToDevice, slot.cap_stream);
@@ -393,13 +393,13 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, bool star, hipSt
         // Small table: it goes in the kernel's arguments, no upload.
         SmallTable st;
         std::memcpy(&st.desc, slot.staging, sizeof(BatchDesc));
-        std::memcpy(st.reqs, static_cast<const char *>(slot.staging) + sizeof(BatchDesc),
+        std::memcpy(st.reqs, static_cast<const char *>(slot.staging) + kReqOffset,
                     (size_t)slot.m_staged * sizeof(BatchReq));
         hipError_t e = launch_batch_small(cfg, st, tabs, star, stream);
         if (e != hipSuccess)
             return hip_fail(e, "batch kernel launch");
     } else {
-        const size_t bytes = sizeof(BatchDesc) + (size_t)slot.m_staged * sizeof(BatchReq);
+        const size_t bytes = kReqOffset + (size_t)slot.m_staged * sizeof(BatchReq);
         RNGX_HIP(hipMemcpyAsync(slot.devtab, slot.staging, bytes, hipMemcpyHostToDevice, stream));
         hipError_t e = launch_batch(cfg, ddesc, tabs, star, stream);
         if (e != hipSuccess)

@@ -83,8 +83,11 @@ __device__ __forceinline__ uint64_t wave_jump(const uint64_t *__restrict__ pow2,
 // candidate and a ballot keeps the chunk that holds the answer (two rounds
 // for 4,096 requests). Used when each wave handles one item: it cuts the
 // latency before the wave's first store (one wave per S = 128 item: 5.6 ->
-// 6.1 TB/s). A persistent wave searches with bisection instead: there the
-// wave search measured three times slower over the whole launch.
+// 6.1 TB/s). A persistent wave searches with bisection instead, which runs
+// on the scalar unit and measured the same there. (The first round always
+// reads the first record; while the records shared a cache line with the
+// work counter, that read queued behind every wave's atomic and the
+// persistent loop ran three times slower.)
 __device__ __forceinline__ uint32_t find_request(g_req *__restrict__ reqs, uint32_t m,
                                                  uint64_t item, uint32_t lane)
 {

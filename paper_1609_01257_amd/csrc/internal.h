@@ -117,6 +117,12 @@ struct BatchDesc {
     uint64_t reserved1[3];
 };
 static_assert(sizeof(BatchDesc) == 64, "BatchDesc layout");
+// Offset of the request records in a staged or device table. The records
+// start one 128-byte L2 line after the descriptor, so that no record shares
+// a line with the work counter, which every wave of a persistent launch
+// updates atomically.
+constexpr size_t kReqOffset = 128;
+static_assert(kReqOffset >= sizeof(BatchDesc) && kReqOffset % 64 == 0, "request offset");
 
 // A batch of at most kSmallReqs requests travels in the kernel's arguments
 // (1,088 bytes) instead of being uploaded: one launch, no copy before it.
@@ -130,7 +136,7 @@ struct SmallTable {
 struct BatchSlot {
     int device = -1;          // the device its buffers, event and graph are on
     uint32_t capacity = 0;    // requests the buffers hold (power of two)
-    void *staging = nullptr;  // page-locked: BatchDesc + capacity BatchReq
+    void *staging = nullptr;  // page-locked: BatchDesc, then capacity BatchReq at kReqOffset
     void *devtab = nullptr;   // device copy of the same
     hipEvent_t done = nullptr; // recorded after the slot's last launch
     hipGraphExec_t exec = nullptr;
