@@ -147,6 +147,7 @@ int generate_locked(Generator &c, uint32_t n_iters, void *out, hipStream_t s, bo
         cfg.chunks = c.n < (1u << 26) ? 4 : (u32 ? 2 : 4);
         cfg.nontemporal = 0;
     }
+    drop_pending_hip_error();
     hipError_t e = launch_gen(cfg, u32,
                               current_scrambler() == RNGX_SCRAMBLE_STAR, c.state, c.n, n_iters,
                               out, s);
@@ -175,6 +176,7 @@ int rngx_init(uint64_t seed, uint32_t n_states)
     if (rc)
         return rc;
     const int tok = prof::begin("INIT_KERNEL", c.lib_stream);
+    drop_pending_hip_error();
     hipError_t e = launch_init(c.state, n_states, seed_mix(seed), c.lib_stream);
     prof::end(tok, c.lib_stream);
     if (e != hipSuccess)

@@ -370,6 +370,7 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, bool star, hipSt
             RNGX_HIP(hipStreamBeginCapture(slot.cap_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e1 = hipMemcpyAsync(slot.devtab, slot.staging, bytes,
                                            hipMemcpyHostToDevice, slot.cap_stream);
+            drop_pending_hip_error();
             hipError_t e2 = launch_batch(cfg, ddesc, tabs, star, slot.cap_stream);
             hipGraph_t graph = nullptr;
             hipError_t e3 = hipStreamEndCapture(slot.cap_stream, &graph);
@@ -395,12 +396,14 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, bool star, hipSt
         std::memcpy(&st.desc, slot.staging, sizeof(BatchDesc));
         std::memcpy(st.reqs, static_cast<const char *>(slot.staging) + kReqOffset,
                     (size_t)slot.m_staged * sizeof(BatchReq));
+        drop_pending_hip_error();
         hipError_t e = launch_batch_small(cfg, st, tabs, star, stream);
         if (e != hipSuccess)
             return hip_fail(e, "batch kernel launch");
     } else {
         const size_t bytes = kReqOffset + (size_t)slot.m_staged * sizeof(BatchReq);
         RNGX_HIP(hipMemcpyAsync(slot.devtab, slot.staging, bytes, hipMemcpyHostToDevice, stream));
+        drop_pending_hip_error();
         hipError_t e = launch_batch(cfg, ddesc, tabs, star, stream);
         if (e != hipSuccess)
             return hip_fail(e, "batch kernel launch");
@@ -438,6 +441,7 @@ int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *r
     RNGX_HIP(hipGetDevice(&dev));
     DevTables &t = G().dev[dev];
     RNGX_HIP(hipMemsetAsync(t.d_acc, 0, sizeof(uint64_t), s));
+    drop_pending_hip_error();
     RNGX_HIP(launch_checksum(data, n, t.d_acc, s));
     RNGX_HIP(hipMemcpyAsync(t.h_acc, t.d_acc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     RNGX_HIP(hipStreamSynchronize(s));

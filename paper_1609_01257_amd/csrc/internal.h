@@ -198,6 +198,13 @@ const uint64_t *jump_tables();
 uint64_t jump_host(uint64_t x, uint64_t k);
 void power_rows(uint64_t k, uint64_t *rows_out);
 
+// The launchers below report a launch's status with hipGetLastError, which
+// also returns an older error that no call has consumed yet. Every library
+// call checks its own HIP return codes, so an error still pending there
+// belongs to someone else: drop it right before a launch so that the launch
+// reports only its own status. (Device faults are sticky and still reported.)
+inline void drop_pending_hip_error() { (void)hipGetLastError(); }
+
 // ---- kernel launchers (kernels.hip) ---------------------------------------
 hipError_t launch_init(uint64_t *state, uint32_t n, const SeedMix &mix, hipStream_t s);
 hipError_t launch_gen(const rngx_launch &cfg, bool u32, bool star, uint64_t *state, uint32_t n,

@@ -195,6 +195,7 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
         // it marks the generation's end, so no event of our own is queued.
         RNGX_HIP(hipStreamWaitEvent(cs, g.state_ready, 0));
         const int tok = prof::begin("READ_BUFFER", cs);
+        drop_pending_hip_error();
         hipError_t e = hmapped
                            ? launch_d2h(dev[b], hmapped + (size_t)slot * step_bytes, step_bytes,
                                         g.copy_blocks, cs)

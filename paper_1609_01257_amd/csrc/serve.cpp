@@ -576,6 +576,7 @@ extern "C" int rngx_serve_start(uint64_t seed, uint32_t n_states, void *pool, ui
         // The resident base states: the init kernel, once.
         hipStream_t s0 = s.streams[0];
         const int tok = prof::begin("INIT_KERNEL", s0);
+        drop_pending_hip_error();
         e = launch_init(s.d_states, n_states, seed_mix(seed), s0);
         prof::end(tok, s0);
         if (e == hipSuccess)
