@@ -415,11 +415,11 @@ int rngx_serve_run_trace(const double *arrival_s, const uint32_t *stream_id,
  * Errors: RNGX_E_INVAL if max_pending == 0. */
 int rngx_serve_set_max_pending(uint64_t max_pending);
 
-/* Bound on batches in flight (launched and not yet complete; default 3, kept
+/* Bound on batches in flight (launched and not yet complete; default 2, kept
  * across restarts). While that many run, newly admitted requests wait and
  * join the next batch: under load batches grow instead of many small ones
- * competing on the device, and batches stay queued behind the running one.
- * Errors: RNGX_E_INVAL unless 1 <= max_inflight <= 32. */
+ * competing on the device, and one batch stays queued behind the running
+ * one. Errors: RNGX_E_INVAL unless 1 <= max_inflight <= 32. */
 int rngx_serve_set_max_inflight(uint32_t max_inflight);
 
 /* Stop the server: requests not yet launched are dropped, launched batches

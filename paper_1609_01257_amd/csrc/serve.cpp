@@ -94,7 +94,7 @@ struct Server {
     std::vector<hipStream_t> streams;
     uint32_t max_batch = 1024;
     uint64_t max_pending = 1u << 20;
-    uint32_t max_inflight = 3;
+    uint32_t max_inflight = 2;
     bool star = false; // the output scrambler, fixed at start
     rngx_batch_cfg cfg{256, 4, 0, 0, 16, 1, 0};
     std::thread worker;

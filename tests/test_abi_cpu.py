@@ -234,7 +234,7 @@ def test_serve_max_inflight_validation():
     assert L.rngx_serve_set_max_inflight(0) == rngx.RNGX_E_INVAL
     assert L.rngx_serve_set_max_inflight(33) == rngx.RNGX_E_INVAL
     assert L.rngx_serve_set_max_inflight(32) == rngx.RNGX_OK
-    assert L.rngx_serve_set_max_inflight(3) == rngx.RNGX_OK
+    assert L.rngx_serve_set_max_inflight(2) == rngx.RNGX_OK
 
 
 def test_server_pool_ring_and_ticket_table_model(tmp_path):
