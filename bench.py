@@ -226,7 +226,7 @@ def batched(torch, rngx, steps):
 
 def serving(torch, rngx, seconds, plain_gbs):
     """Serving: 2^20 resident streams, a 16 GB pool with memory-based
-    admission, 4 streams, batches of up to 2,048 requests with at most 3 in
+    admission, 4 streams, batches of up to 2,048 requests with at most 2 in
     flight, Poisson arrivals at 2k / 10k / 50k req/s (stream id uniform,
     length log-uniform in [2^12, 2^22)), results released on completion;
     then a saturation run (a pre-filled backlog) for throughput."""
