@@ -419,7 +419,8 @@ int rngx_serve_set_max_pending(uint64_t max_pending);
  * across restarts). While that many run, newly admitted requests wait and
  * join the next batch: under load batches grow instead of many small ones
  * competing on the device, and one batch stays queued behind the running
- * one. Errors: RNGX_E_INVAL unless 1 <= max_inflight <= 32. */
+ * one. A batch of at most 2^20 values, which is latency-bound, may run one
+ * above the bound. Errors: RNGX_E_INVAL unless 1 <= max_inflight <= 32. */
 int rngx_serve_set_max_inflight(uint32_t max_inflight);
 
 /* Stop the server: requests not yet launched are dropped, launched batches

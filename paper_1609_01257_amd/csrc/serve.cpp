@@ -168,6 +168,9 @@ bool admit(Server &s)
     return progress;
 }
 
+// Batches of at most this many (padded) values are latency-bound.
+constexpr uint64_t kSmallBatchValues = 1u << 20;
+
 // Launch schedule of a served batch of `values` (padded) values. Small
 // batches are latency-bound: one wave per 4,096-value item gets every wave
 // storing soonest. Larger ones run on the persistent grid with S = 256,
@@ -175,9 +178,25 @@ bool admit(Server &s)
 // 243 GB: 5.45-5.51 TB/s against 4.90-4.97 for one wave per item).
 void serve_schedule(uint64_t values, rngx_batch_cfg &cfg)
 {
-    const bool small = values <= (1u << 20);
+    const bool small = values <= kSmallBatchValues;
     cfg.values_per_lane = small ? 64u : 256u;
     cfg.per_item = small ? 1u : 0u;
+}
+
+// Whether the next batch (the first max_batch admitted requests, padded as
+// launch_admitted pads them) would be small.
+bool next_batch_small(Server &s)
+{
+    uint64_t values = 0;
+    uint32_t k = 0;
+    for (uint64_t tk : s.admitted) {
+        if (k++ == s.max_batch)
+            break;
+        values += (s.reqs.find(tk)->length + 15) & ~(uint64_t)15;
+        if (values > kSmallBatchValues)
+            return false;
+    }
+    return true;
 }
 
 int launch_admitted(Server &s, Flight &f, std::vector<StageReq> &items, const SeedMix &mix)
@@ -268,7 +287,12 @@ void worker_main(Server *sp)
             uint32_t inflight = 0;
             for (const Flight &f : s.flights)
                 inflight += f.busy;
-            if (inflight >= s.max_inflight)
+            // The cap keeps throughput-bound batches from competing on the
+            // device; a small, latency-bound batch may run one above it
+            // rather than wait (at 50k req/s with a cap of 2 and no such
+            // allowance, p50 latency measured 28-45 us).
+            if (inflight >= s.max_inflight &&
+                (inflight > s.max_inflight || !next_batch_small(s)))
                 break;
             // An idle slot on the stream with the fewest batches in flight.
             Flight *idle = nullptr;
