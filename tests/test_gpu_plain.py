@@ -189,6 +189,25 @@ def test_size_overflow_rejected():
     torch.cuda.empty_cache()
 
 
+def test_largest_state_count_sampled(oracle):
+    # n = 2^32 - 1 work-items (the most a 32-bit count allows), 2 iterations:
+    # the last, partial wave (511 work-items) and a second row that starts
+    # 8 bytes off a 16-byte boundary; sampled values against the oracle.
+    n, seed = 2**32 - 1, 7
+    rngx.init(seed, n)
+    out = torch.empty(2 * n, dtype=torch.int64, device="cuda")
+    rngx.generate(2, out)
+    gids = [0, 1, 2, 511, 512, 1 << 31, 123456789, n - 513, n - 512, n - 511, n - 2, n - 1]
+    pos = [(k, g) for k in (0, 1) for g in gids]
+    idx = torch.tensor([k * n + g for k, g in pos], device="cuda")
+    got = out.index_select(0, idx).cpu().numpy().view(np.uint64)
+    del out
+    rngx.shutdown()
+    torch.cuda.empty_cache()
+    for (k, g), v in zip(pos, got):
+        assert int(v) == oracle.value(seed, g, k), (k, g)
+
+
 def test_shutdown_releases_device_memory():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
