@@ -47,6 +47,18 @@ def test_generate_before_init_is_noinit():
         rngx.info()
 
 
+def test_host_seeding_applies_the_zero_fixup():
+    # The library's host-side seeding, on the (seed, gid) pair whose hashed
+    # state is zero, against the oracle.
+    import oracle
+    from tests.test_oracle_pins import inverse_hash_high, inverse_hash_low
+    g_star = inverse_hash_low(0)
+    seed = inverse_hash_high(inverse_hash_high(0) ^ oracle.hash_high(0)) << 32
+    assert rngx.initial_state(seed, g_star) == oracle.init_state(seed, g_star)
+    assert rngx.initial_state(seed, g_star) == oracle.hash_high(0) << 32
+    assert rngx.initial_state(seed, g_star ^ 1) == oracle.init_state(seed, g_star ^ 1)
+
+
 def test_profile_window_before_init_is_noinit():
     rngx.shutdown()
     L = rngx.lib()

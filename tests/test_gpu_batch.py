@@ -170,6 +170,26 @@ def test_autotune_agrees_across_candidates(oracle):
                           oracle.generate_batch(_oracle_reqs(oracle, r)))
 
 
+def test_zero_state_fixup_on_the_device(oracle):
+    # The one gid whose hashed state is zero under a seed with lo32 = 0 and
+    # a chosen hi32 (built from the hashes' inverses, as in the oracle pin)
+    # must start from the replacement state W(0) << 32 on the device too.
+    from tests.test_oracle_pins import inverse_hash_high, inverse_hash_low
+    g_star = inverse_hash_low(0)
+    h_needed = inverse_hash_high(0)
+    seed = inverse_hash_high(h_needed ^ oracle.hash_high(0)) << 32
+    assert oracle.init_state(seed, g_star) == oracle.hash_high(0) << 32
+    gids = [g_star, g_star ^ 1, g_star, g_star]
+    offsets = [0, 0, 12345, 1000003]
+    lengths = [100, 100, 50, 70]
+    exp = oracle.generate_batch(oracle.make_reqs([seed] * 4, gids, offsets, lengths))
+    assert exp[0] == oracle.hash_high(0) << 32
+    for S, per_item in ((64, True), (256, False)):
+        rngx.set_batch_cfg(S, 4, 0, False, 16, 1, per_item)
+        got = _run(rngx.make_reqs([seed] * 4, gids, offsets, lengths), sum(lengths))
+        assert np.array_equal(got, exp), (S, per_item)
+
+
 def test_batch_errors_on_device():
     r = rngx.make_reqs([1, 2], [0, 1], [0, 0], [10, 20])
     out = torch.zeros(64, dtype=torch.int64, device="cuda")
