@@ -194,7 +194,9 @@ typedef int (*rngx_consume_fn)(void *user, uint64_t step, const void *values, si
  *       consumer returned for the step it held.
  * gen_stream, copy_stream: distinct streams, or NULL for the library's own
  *       pair. The call returns when every copy has completed (and every
- *       step has been consumed).
+ *       step has been consumed); on an error or a stop it first waits for
+ *       all the work it enqueued on both streams, so no kernel or copy
+ *       still uses the buffers when it returns.
  * Errors: RNGX_E_NOINIT; RNGX_E_INVAL (NULL/equal/misaligned buffers, a
  * step larger than dev_bytes, host_slots == 0, equal streams);
  * RNGX_E_ABORTED when the consumer stops the stream (steps generated so far
