@@ -121,6 +121,26 @@ const char *rngx_last_error(void);
 /* Static name of a status code (the paper's errors module, Section 4.4). */
 const char *rngx_strerror(int code);
 
+/* HIP errors that no call could return (the paper reports every error to
+ * the caller, Section 4.1; these are the ones with no caller left to
+ * receive them). Two kinds are recorded, each with the place it was met,
+ * the HIP error name and the host thread:
+ *  - "released": a HIP call of the library's own release paths failed
+ *    (freeing buffers, destroying streams, events and graphs, the waits
+ *    before them) inside a call that still succeeded or was already
+ *    failing for another reason;
+ *  - "stray": an error was pending in the calling thread when the library
+ *    was about to launch a kernel, left by an earlier HIP call that is not
+ *    the library's (every library call consumes the status of its own HIP
+ *    calls); it is recorded and cleared, so that the launch reports only
+ *    its own status.
+ * *released and *stray (either may be NULL) receive the counts since the
+ * last clear; text (may be NULL) receives up to cap - 1 bytes of the most
+ * recent notes (at most 32, one per line, oldest first), NUL-terminated.
+ * clear != 0 resets counts and notes after reading them.
+ * Errors: RNGX_E_INVAL if text is non-NULL and cap == 0. */
+int rngx_hip_notes(uint64_t *released, uint64_t *stray, char *text, size_t cap, int clear);
+
 /* ------------------------------------------------------------------------ */
 /* Launch configuration of the plain generator                               */
 /* ------------------------------------------------------------------------ */
@@ -513,7 +533,7 @@ int rngx_profile_events(rngx_prof_event *out, uint32_t cap, uint32_t *n_out);
 int rngx_profile_analyze(const rngx_prof_event *events, uint32_t n,
                          double elapsed_s, rngx_prof_stats *out);
 
-/* Export formats of an event table (Section 4.4: the profiler can write a
+/* Export formats of an event table (Section 4.3: the profiler can write a
  * table of queue name, start instant, end instant and event name to a text
  * file for a queue-utilisation chart, as in Fig. 5).
  * RNGX_EXPORT_TABLE: tab-separated text, a header line

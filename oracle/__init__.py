@@ -72,6 +72,12 @@ def lib():
         L.oracle_generate_star_u32.restype = u64
         L.oracle_generate_batch.argtypes = [p, u32, p]
         L.oracle_generate_batch.restype = u64
+        L.oracle_seed_range.argtypes = [u64, u32, u64, u64, p]
+        L.oracle_seed_range.restype = None
+        L.oracle_emit_rows.argtypes = [p, u64, u32, ctypes.c_int, p, u64]
+        L.oracle_emit_rows.restype = u64
+        L.oracle_generate_range.argtypes = [u64, u64, u64, u64, u32, p]
+        L.oracle_generate_range.restype = u64
         L.oracle_hash_low_range.argtypes = [u32, u64, p]
         L.oracle_hash_low_range.restype = None
         L.oracle_hash_high_range.argtypes = [u32, u64, p]
@@ -163,6 +169,46 @@ def generate_star_u32(seed: int, n: int, n_iters: int, cursor: int = 0) -> np.nd
     return out
 
 
+# Words oracle_emit_rows can emit: the state, its low half, the scrambled
+# word, the high half of the scrambled word.
+WORD_U64, WORD_U32, WORD_STAR, WORD_STAR_U32 = 0, 1, 2, 3
+
+
+def seed_range(seed: int, g0: int, count: int, cursor: int = 0) -> np.ndarray:
+    """States of work-items g0 .. g0+count-1 at value number ``cursor``
+    (sequential steps from each initial state)."""
+    if g0 < 0 or count < 0 or g0 + count > 1 << 32:
+        raise ValueError("work-items must lie in [0, 2^32)")
+    st = np.empty(count, dtype=np.uint64)
+    lib().oracle_seed_range(seed, g0, count, cursor, _ptr(st))
+    return st
+
+
+def emit_rows(states: np.ndarray, n_rows: int, word: int = WORD_U64) -> np.ndarray:
+    """Continue the plain loop from ``states`` (advanced in place): n_rows
+    rows, each emitting every state and then stepping it."""
+    if states.dtype != np.uint64 or not states.flags["C_CONTIGUOUS"]:
+        raise ValueError("states must be a contiguous uint64 array")
+    dt = np.uint32 if word in (WORD_U32, WORD_STAR_U32) else np.uint64
+    out = np.empty((n_rows, states.size), dtype=dt)
+    zeros = lib().oracle_emit_rows(_ptr(states), states.size, n_rows, word, _ptr(out),
+                                   states.size)
+    if zeros:
+        raise AssertionError("oracle met %d zero states" % zeros)
+    return out
+
+
+def generate_range(seed: int, g0: int, g1: int, n_iters: int, cursor: int = 0) -> np.ndarray:
+    """Columns g0 <= g < g1 of :func:`generate` (iteration-major)."""
+    if not 0 <= g0 <= g1 <= 1 << 32:
+        raise ValueError("need 0 <= g0 <= g1 <= 2^32")
+    out = np.empty((n_iters, g1 - g0), dtype=np.uint64)
+    zeros = lib().oracle_generate_range(seed, g0, g1, cursor, n_iters, _ptr(out))
+    if zeros:
+        raise AssertionError("oracle produced %d zero values" % zeros)
+    return out
+
+
 def make_reqs(seeds, gids, offsets, lengths) -> np.ndarray:
     m = len(lengths)
     r = np.zeros(m, dtype=REQ_DTYPE)
@@ -184,6 +230,19 @@ def generate_batch(reqs: np.ndarray) -> np.ndarray:
     return out
 
 
+def serve_offsets(submissions) -> list:
+    """First value number of each served request (the bookkeeping rule of
+    :func:`serve_expected`): the sum of the lengths of the requests submitted
+    to the same stream before it."""
+    cursor = {}
+    offs = []
+    for g, length in submissions:
+        c = cursor.get(g, 0)
+        offs.append(c)
+        cursor[g] = c + int(length)
+    return offs
+
+
 def serve_expected(seed: int, submissions) -> list:
     """Outputs of served requests, given the submission history.
 
@@ -193,12 +252,7 @@ def serve_expected(seed: int, submissions) -> list:
     (sum of the lengths of g's earlier requests). Returns one uint64 array per
     request, in submission order.
     """
-    cursor = {}
-    offs = []
-    for g, length in submissions:
-        c = cursor.get(g, 0)
-        offs.append(c)
-        cursor[g] = c + int(length)
+    offs = serve_offsets(submissions)
     reqs = make_reqs([seed] * len(offs), [g for g, _ in submissions], offs,
                      [int(length) for _, length in submissions])
     flat = generate_batch(reqs)

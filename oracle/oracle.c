@@ -251,6 +251,73 @@ uint64_t oracle_generate_star_u32(uint64_t seed, uint32_t n, uint64_t cursor,
 }
 
 /* ------------------------------------------------------------------------- */
+/* The same output, a slice at a time: the pieces a checker needs to compare  */
+/* a very large output (gigabytes of rows) with the definition without        */
+/* holding all of it, and to spread the work over host threads by work-item. */
+/* Nothing here jumps ahead: every state is reached by sequential steps.      */
+/* ------------------------------------------------------------------------- */
+
+/* States of work-items g0 .. g0 + count - 1 (wrapping is not allowed: the    */
+/* caller keeps g0 + count <= 2^32) at value number `cursor`, each one        */
+/* stepped `cursor` times from its initial state (Listing S4, then Listing S5 */
+/* once per earlier iteration).                                               */
+void oracle_seed_range(uint64_t seed, uint32_t g0, uint64_t count, uint64_t cursor,
+                       uint64_t *st)
+{
+    for (uint64_t t = 0; t < count; ++t)
+        st[t] = oracle_value(seed, (uint32_t)(g0 + t), cursor);
+}
+
+/* Continue the paper's loop from a caller-held state array: n_rows more      */
+/* iterations over `count` work-items. Iteration k emits every state into     */
+/* row k (out[k * ld + t]), then advances every state one step (Section 5:    */
+/* emit, then advance). On return st holds the next value of every stream,   */
+/* so a second call continues exactly where the first stopped. `word`        */
+/* selects the emitted word: 0 the state, 1 its low 32 bits (into a uint32   */
+/* row), 2 the scrambled word, 3 the high half of the scrambled word (u32).  */
+/* Returns the number of zero states met (never-zero invariant: always 0).   */
+uint64_t oracle_emit_rows(uint64_t *st, uint64_t count, uint32_t n_rows, int word, void *out,
+                          uint64_t ld)
+{
+    uint64_t zeros = 0;
+    uint64_t *o64 = (uint64_t *)out;
+    uint32_t *o32 = (uint32_t *)out;
+    for (uint32_t k = 0; k < n_rows; ++k) {
+        for (uint64_t t = 0; t < count; ++t) {
+            const uint64_t x = st[t];
+            if (x == 0u)
+                ++zeros;
+            const size_t at = (size_t)k * ld + t;
+            switch (word) {
+            case 1: o32[at] = (uint32_t)(x & 0xffffffffu); break;
+            case 2: o64[at] = oracle_scramble(x); break;
+            case 3: o32[at] = (uint32_t)(oracle_scramble(x) >> 32); break;
+            default: o64[at] = x; break;
+            }
+            st[t] = oracle_rng_step(x);
+        }
+    }
+    return zeros;
+}
+
+/* Plain output restricted to work-items g0 <= g < g1 (g1 <= 2^32):           */
+/*     out[k * (g1 - g0) + (g - g0)] = value(seed, g, cursor + k),            */
+/* i.e. the matching columns of oracle_generate. Returns the zero count, or  */
+/* UINT64_MAX if the state array cannot be allocated.                        */
+uint64_t oracle_generate_range(uint64_t seed, uint64_t g0, uint64_t g1, uint64_t cursor,
+                               uint32_t n_iters, uint64_t *out)
+{
+    const uint64_t count = g1 > g0 ? g1 - g0 : 0;
+    uint64_t *st = (uint64_t *)malloc((size_t)count * sizeof(uint64_t) + 1);
+    if (!st)
+        return UINT64_MAX;
+    oracle_seed_range(seed, (uint32_t)g0, count, cursor, st);
+    const uint64_t zeros = oracle_emit_rows(st, count, n_iters, 0, out, count);
+    free(st);
+    return zeros;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Batched streams. Request j names one stream by (seed_j, gid_j) and asks    */
 /* for length_j consecutive values starting at value number offset_j. The     */
 /* outputs are packed one request after another, in request order:           */

@@ -10,9 +10,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <string>
 #include <vector>
+
+#include <sys/syscall.h>
+#include <unistd.h>
 
 #include "internal.h"
 
@@ -33,11 +37,62 @@ int set_error(int code, const char *fmt, ...)
 
 int hip_fail(hipError_t e, const char *what)
 {
+    // The error goes back to the caller through the return code: consume it,
+    // so that an unrelated hipGetLastError (the library's before its next
+    // launch, or the application's) does not report it a second time.
+    (void)hipGetLastError();
     const int code = (e == hipErrorOutOfMemory) ? RNGX_E_NOMEM : RNGX_E_HIP;
     return set_error(code, "%s failed: %s (%s)", what, hipGetErrorName(e), hipGetErrorString(e));
 }
 
 void clear_error() { t_last_error.clear(); }
+
+namespace {
+
+// The notes of rngx_hip_notes: counts since the last clear and the most
+// recent lines.
+struct HipNotes {
+    std::mutex mu;
+    uint64_t released = 0, stray = 0;
+    std::deque<std::string> last;
+};
+constexpr size_t kMaxNotes = 32;
+
+HipNotes &hip_notes()
+{
+    static HipNotes *n = new HipNotes; // never destroyed: used until exit
+    return *n;
+}
+
+void add_note(bool own, const char *what, hipError_t e)
+{
+    char buf[320];
+    std::snprintf(buf, sizeof buf, "%s %s: %s (thread %ld)", own ? "released" : "stray", what,
+                  hipGetErrorName(e), (long)syscall(SYS_gettid));
+    HipNotes &n = hip_notes();
+    std::lock_guard<std::mutex> lk(n.mu);
+    ++(own ? n.released : n.stray);
+    n.last.emplace_back(buf);
+    if (n.last.size() > kMaxNotes)
+        n.last.pop_front();
+}
+
+} // namespace
+
+void note_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess)
+        return;
+    (void)hipGetLastError(); // this call's own error, recorded below
+    add_note(true, what, e);
+}
+
+void take_stray_error(const char *where)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        add_note(false, where, e);
+}
 
 Generator &generator()
 {
@@ -75,8 +130,8 @@ int fresh_state_locked(Generator &c, uint32_t n_states, const char *who)
         // Resources belong to another device: recreate them here (the
         // streaming pipeline's streams and events on first use).
         release_pipeline_locked(c);
-        (void)hipStreamDestroy(c.lib_stream);
-        (void)hipEventDestroy(c.state_ready);
+        RNGX_NOTE(hipStreamDestroy(c.lib_stream));
+        RNGX_NOTE(hipEventDestroy(c.state_ready));
         c.lib_stream = nullptr;
         c.state_ready = nullptr;
     }
@@ -88,7 +143,7 @@ int fresh_state_locked(Generator &c, uint32_t n_states, const char *who)
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, (size_t)n_states * sizeof(uint64_t));
     if (e != hipSuccess) {
-        (void)hipGetLastError();
+        (void)hipGetLastError(); // this allocation's own error, reported below
         return set_error(RNGX_E_NOMEM, "%s: cannot allocate %zu bytes of state: %s", who,
                          (size_t)n_states * sizeof(uint64_t), hipGetErrorString(e));
     }
@@ -147,7 +202,7 @@ int generate_locked(Generator &c, uint32_t n_iters, void *out, hipStream_t s, bo
         cfg.chunks = c.n < (1u << 26) ? 4 : (u32 ? 2 : 4);
         cfg.nontemporal = 0;
     }
-    drop_pending_hip_error();
+    take_stray_error("before the rng kernel launch");
     hipError_t e = launch_gen(cfg, u32,
                               current_scrambler() == RNGX_SCRAMBLE_STAR, c.state, c.n, n_iters,
                               out, s);
@@ -176,7 +231,7 @@ int rngx_init(uint64_t seed, uint32_t n_states)
     if (rc)
         return rc;
     const int tok = prof::begin("INIT_KERNEL", c.lib_stream);
-    drop_pending_hip_error();
+    take_stray_error("before the init kernel launch");
     hipError_t e = launch_init(c.state, n_states, seed_mix(seed), c.lib_stream);
     prof::end(tok, c.lib_stream);
     if (e != hipSuccess)
@@ -273,9 +328,9 @@ int rngx_shutdown(void)
     release_batch();
     prof::release_all();
     if (c.state_ready)
-        (void)hipEventDestroy(c.state_ready);
+        RNGX_NOTE(hipEventDestroy(c.state_ready));
     if (c.lib_stream)
-        (void)hipStreamDestroy(c.lib_stream);
+        RNGX_NOTE(hipStreamDestroy(c.lib_stream));
     c.state_ready = nullptr;
     c.lib_stream = nullptr;
     c.device = -1;
@@ -283,6 +338,32 @@ int rngx_shutdown(void)
 }
 
 const char *rngx_last_error(void) { return t_last_error.c_str(); }
+
+int rngx_hip_notes(uint64_t *released, uint64_t *stray, char *text, size_t cap, int clear)
+{
+    clear_error();
+    if (text && cap == 0)
+        return set_error(RNGX_E_INVAL, "rngx_hip_notes: text given with cap 0");
+    HipNotes &n = hip_notes();
+    std::lock_guard<std::mutex> lk(n.mu);
+    if (released)
+        *released = n.released;
+    if (stray)
+        *stray = n.stray;
+    if (text) {
+        std::string all;
+        for (const std::string &l : n.last)
+            all += l + "\n";
+        const size_t k = std::min(all.size(), cap - 1);
+        std::memcpy(text, all.data(), k);
+        text[k] = 0;
+    }
+    if (clear) {
+        n.released = n.stray = 0;
+        n.last.clear();
+    }
+    return RNGX_OK;
+}
 
 const char *rngx_strerror(int code)
 {

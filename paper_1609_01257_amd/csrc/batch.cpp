@@ -61,15 +61,15 @@ BatchGlobals &G()
 void free_tables(DevTables &t)
 {
     if (t.d_pow2)
-        (void)hipFree(t.d_pow2);
+        RNGX_NOTE(hipFree(t.d_pow2));
     if (t.d_spread)
-        (void)hipFree(t.d_spread);
+        RNGX_NOTE(hipFree(t.d_spread));
     if (t.d_carry_nib)
-        (void)hipFree(t.d_carry_nib);
+        RNGX_NOTE(hipFree(t.d_carry_nib));
     if (t.d_acc)
-        (void)hipFree(t.d_acc);
+        RNGX_NOTE(hipFree(t.d_acc));
     if (t.h_acc)
-        (void)hipHostFree(t.h_acc);
+        RNGX_NOTE(hipHostFree(t.h_acc));
     t = DevTables();
 }
 
@@ -121,17 +121,17 @@ void build_host_tables(std::vector<uint64_t> &spread, std::vector<uint64_t> &nib
 void free_slot(BatchSlot &s)
 {
     if (s.done)
-        (void)hipEventSynchronize(s.done);
+        RNGX_NOTE(hipEventSynchronize(s.done));
     if (s.exec)
-        (void)hipGraphExecDestroy(s.exec);
+        RNGX_NOTE(hipGraphExecDestroy(s.exec));
     if (s.staging)
-        (void)hipHostFree(s.staging);
+        RNGX_NOTE(hipHostFree(s.staging));
     if (s.devtab)
-        (void)hipFree(s.devtab);
+        RNGX_NOTE(hipFree(s.devtab));
     if (s.done)
-        (void)hipEventDestroy(s.done);
+        RNGX_NOTE(hipEventDestroy(s.done));
     if (s.cap_stream)
-        (void)hipStreamDestroy(s.cap_stream);
+        RNGX_NOTE(hipStreamDestroy(s.cap_stream));
     s = BatchSlot();
 }
 
@@ -218,13 +218,13 @@ int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
         if (slot.done)
             RNGX_HIP(hipEventSynchronize(slot.done));
         if (slot.exec) {
-            (void)hipGraphExecDestroy(slot.exec);
+            RNGX_NOTE(hipGraphExecDestroy(slot.exec));
             slot.exec = nullptr;
         }
         if (slot.staging)
-            (void)hipHostFree(slot.staging);
+            RNGX_NOTE(hipHostFree(slot.staging));
         if (slot.devtab)
-            (void)hipFree(slot.devtab);
+            RNGX_NOTE(hipFree(slot.devtab));
         slot.staging = slot.devtab = nullptr;
         slot.capacity = 0;
         const size_t bytes = kReqOffset + (size_t)cap * sizeof(BatchReq);
@@ -235,7 +235,7 @@ int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
         }
         e = hipMalloc(&slot.devtab, bytes);
         if (e != hipSuccess) {
-            (void)hipHostFree(slot.staging);
+            RNGX_NOTE(hipHostFree(slot.staging));
             slot.staging = slot.devtab = nullptr;
             return hip_fail(e, "hipMalloc (batch table)");
         }
@@ -361,7 +361,7 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, bool star, hipSt
                           slot.exec_cfg.per_item == cfg.per_item && slot.exec_star == star;
         if (!same) {
             if (slot.exec) {
-                (void)hipGraphExecDestroy(slot.exec);
+                RNGX_NOTE(hipGraphExecDestroy(slot.exec));
                 slot.exec = nullptr;
             }
             if (!slot.cap_stream)
@@ -370,18 +370,19 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, bool star, hipSt
             RNGX_HIP(hipStreamBeginCapture(slot.cap_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e1 = hipMemcpyAsync(slot.devtab, slot.staging, bytes,
                                            hipMemcpyHostToDevice, slot.cap_stream);
-            drop_pending_hip_error();
+            // (e1 is consumed here if it failed: it is reported below.)
+            take_stray_error("before the captured batch kernel launch");
             hipError_t e2 = launch_batch(cfg, ddesc, tabs, star, slot.cap_stream);
             hipGraph_t graph = nullptr;
             hipError_t e3 = hipStreamEndCapture(slot.cap_stream, &graph);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
                 if (graph)
-                    (void)hipGraphDestroy(graph);
+                    RNGX_NOTE(hipGraphDestroy(graph));
                 return hip_fail(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3),
                                 "batch graph capture");
             }
             hipError_t e4 = hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
+            RNGX_NOTE(hipGraphDestroy(graph));
             if (e4 != hipSuccess) {
                 slot.exec = nullptr;
                 return hip_fail(e4, "hipGraphInstantiate (batch)");
@@ -396,14 +397,14 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, bool star, hipSt
         std::memcpy(&st.desc, slot.staging, sizeof(BatchDesc));
         std::memcpy(st.reqs, static_cast<const char *>(slot.staging) + kReqOffset,
                     (size_t)slot.m_staged * sizeof(BatchReq));
-        drop_pending_hip_error();
+        take_stray_error("before the batch kernel launch");
         hipError_t e = launch_batch_small(cfg, st, tabs, star, stream);
         if (e != hipSuccess)
             return hip_fail(e, "batch kernel launch");
     } else {
         const size_t bytes = kReqOffset + (size_t)slot.m_staged * sizeof(BatchReq);
         RNGX_HIP(hipMemcpyAsync(slot.devtab, slot.staging, bytes, hipMemcpyHostToDevice, stream));
-        drop_pending_hip_error();
+        take_stray_error("before the batch kernel launch");
         hipError_t e = launch_batch(cfg, ddesc, tabs, star, stream);
         if (e != hipSuccess)
             return hip_fail(e, "batch kernel launch");
@@ -421,15 +422,15 @@ void release_batch()
     std::lock_guard<std::mutex> lk(g.mu);
     free_slot(g.api_slot);
     int cur = -1;
-    (void)hipGetDevice(&cur);
+    RNGX_NOTE(hipGetDevice(&cur));
     for (int d = 0; d < kMaxDevices; ++d) {
         if (!g.dev[d].d_pow2)
             continue;
-        (void)hipSetDevice(d);
+        RNGX_NOTE(hipSetDevice(d));
         free_tables(g.dev[d]);
     }
     if (cur >= 0)
-        (void)hipSetDevice(cur);
+        RNGX_NOTE(hipSetDevice(cur));
 }
 
 int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *result)
@@ -441,7 +442,7 @@ int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *r
     RNGX_HIP(hipGetDevice(&dev));
     DevTables &t = G().dev[dev];
     RNGX_HIP(hipMemsetAsync(t.d_acc, 0, sizeof(uint64_t), s));
-    drop_pending_hip_error();
+    take_stray_error("before the checksum kernel launch");
     RNGX_HIP(launch_checksum(data, n, t.d_acc, s));
     RNGX_HIP(hipMemcpyAsync(t.h_acc, t.d_acc, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     RNGX_HIP(hipStreamSynchronize(s));
@@ -531,8 +532,8 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
         hipEvent_t a, b;
         ~Events()
         {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
+            RNGX_NOTE(hipEventDestroy(a));
+            RNGX_NOTE(hipEventDestroy(b));
         }
     } guard{e0, e1};
 

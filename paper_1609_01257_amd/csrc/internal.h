@@ -198,12 +198,20 @@ const uint64_t *jump_tables();
 uint64_t jump_host(uint64_t x, uint64_t k);
 void power_rows(uint64_t k, uint64_t *rows_out);
 
-// The launchers below report a launch's status with hipGetLastError, which
+// HIP errors with no caller to return them to (rngx_hip_notes).
+// note_hip: the status of one of the library's own HIP calls on a release
+// path. A failure is consumed (so that it is not reported later by an
+// unrelated hipGetLastError, the library's or the application's) and
+// recorded with `what`.
+void note_hip(hipError_t e, const char *what);
+#define RNGX_NOTE(call) ::rngx::note_hip((call), #call)
+// The launchers below read a launch's status with hipGetLastError, which
 // also returns an older error that no call has consumed yet. Every library
-// call checks its own HIP return codes, so an error still pending there
-// belongs to someone else: drop it right before a launch so that the launch
-// reports only its own status. (Device faults are sticky and still reported.)
-inline void drop_pending_hip_error() { (void)hipGetLastError(); }
+// call consumes the status of its own HIP calls, so an error still pending
+// right before a launch was left by someone else: take_stray_error records
+// it (with `where`) and clears it, so that the launch reports only its own
+// status. (Device faults are sticky and are still reported by the launch.)
+void take_stray_error(const char *where);
 
 // ---- kernel launchers (kernels.hip) ---------------------------------------
 hipError_t launch_init(uint64_t *state, uint32_t n, const SeedMix &mix, hipStream_t s);

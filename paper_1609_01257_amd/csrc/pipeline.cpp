@@ -27,18 +27,18 @@ namespace rngx {
 void release_pipeline_locked(Generator &g)
 {
     if (g.pipe_copy)
-        (void)hipStreamSynchronize(g.pipe_copy);
+        RNGX_NOTE(hipStreamSynchronize(g.pipe_copy));
     if (g.pipe_gen)
-        (void)hipStreamSynchronize(g.pipe_gen);
+        RNGX_NOTE(hipStreamSynchronize(g.pipe_gen));
     for (int i = 0; i < 2; ++i) {
         if (g.copy_done[i])
-            (void)hipEventDestroy(g.copy_done[i]);
+            RNGX_NOTE(hipEventDestroy(g.copy_done[i]));
         g.copy_done[i] = nullptr;
     }
     if (g.pipe_gen)
-        (void)hipStreamDestroy(g.pipe_gen);
+        RNGX_NOTE(hipStreamDestroy(g.pipe_gen));
     if (g.pipe_copy)
-        (void)hipStreamDestroy(g.pipe_copy);
+        RNGX_NOTE(hipStreamDestroy(g.pipe_copy));
     g.pipe_gen = g.pipe_copy = nullptr;
 }
 
@@ -62,7 +62,7 @@ struct SlotEvents {
     ~SlotEvents()
     {
         for (hipEvent_t e : ev)
-            (void)hipEventDestroy(e);
+            RNGX_NOTE(hipEventDestroy(e));
     }
 };
 
@@ -144,7 +144,7 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
         if (hipHostGetDevicePointer(&p, host, 0) == hipSuccess && p)
             hmapped = static_cast<char *>(p);
         else
-            (void)hipGetLastError(); // not page-locked: use the runtime copy
+            (void)hipGetLastError(); // its own error: not page-locked, so use the runtime copy
     }
 
     SlotEvents slots;
@@ -160,13 +160,26 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
     // streams, so that no kernel or copy still uses the caller's buffers
     // when the call returns.
     auto drain = [&]() {
-        (void)hipStreamSynchronize(gs);
-        (void)hipStreamSynchronize(cs);
+        RNGX_NOTE(hipStreamSynchronize(gs));
+        RNGX_NOTE(hipStreamSynchronize(cs));
     };
+
+    // A failed HIP call once work is queued: report it, after the drain.
+    auto fail = [&](hipError_t e, const char *what) -> int {
+        const int code = hip_fail(e, what);
+        drain();
+        return code;
+    };
+#define PIPE_HIP(call)                                   \
+    do {                                                 \
+        const hipError_t pipe_e_ = (call);               \
+        if (pipe_e_ != hipSuccess)                       \
+            return fail(pipe_e_, #call);                 \
+    } while (0)
 
     auto consume_step = [&](uint64_t k) -> int {
         const uint32_t slot = (uint32_t)(k % host_slots);
-        RNGX_HIP(hipEventSynchronize(slots.ev[slot]));
+        PIPE_HIP(hipEventSynchronize(slots.ev[slot]));
         if (consume(user, k, hbase + (size_t)slot * step_bytes, step_bytes) != 0)
             return set_error(RNGX_E_ABORTED, "stream_to_host: consumer stopped the stream at step "
                                              "%llu",
@@ -185,7 +198,7 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
             }
         }
         if (k >= 2)
-            RNGX_HIP(hipStreamWaitEvent(gs, copy_dep[b], 0));
+            PIPE_HIP(hipStreamWaitEvent(gs, copy_dep[b], 0));
         rc = generate_locked(g, iters_per_step, dev[b], gs, u32 != 0);
         if (rc) {
             drain();
@@ -193,9 +206,9 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
         }
         // generate_locked recorded state_ready on gs right after the kernel:
         // it marks the generation's end, so no event of our own is queued.
-        RNGX_HIP(hipStreamWaitEvent(cs, g.state_ready, 0));
+        PIPE_HIP(hipStreamWaitEvent(cs, g.state_ready, 0));
         const int tok = prof::begin("READ_BUFFER", cs);
-        drop_pending_hip_error();
+        take_stray_error("before the device-to-host copy");
         hipError_t e = hmapped
                            ? launch_d2h(dev[b], hmapped + (size_t)slot * step_bytes, step_bytes,
                                         g.copy_blocks, cs)
@@ -204,17 +217,15 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
         // The profiler's end event of the copy, when there is one, also
         // orders generation k + 2 after it (one marker fewer per step).
         hipEvent_t copied = prof::end_event(tok, cs);
-        if (e != hipSuccess) {
-            drain();
-            return hip_fail(e, hmapped ? "device-to-host copy kernel" : "hipMemcpyAsync (D2H)");
-        }
+        if (e != hipSuccess)
+            return fail(e, hmapped ? "device-to-host copy kernel" : "hipMemcpyAsync (D2H)");
         if (!copied) {
-            RNGX_HIP(hipEventRecord(g.copy_done[b], cs));
+            PIPE_HIP(hipEventRecord(g.copy_done[b], cs));
             copied = g.copy_done[b];
         }
         copy_dep[b] = copied;
         if (consume)
-            RNGX_HIP(hipEventRecord(slots.ev[slot], cs));
+            PIPE_HIP(hipEventRecord(slots.ev[slot], cs));
     }
     if (consume) {
         const uint64_t first = n_steps > host_slots ? n_steps - host_slots : 0;
@@ -226,6 +237,7 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
             }
         }
     }
-    RNGX_HIP(hipStreamSynchronize(cs));
+    PIPE_HIP(hipStreamSynchronize(cs));
+#undef PIPE_HIP
     return RNGX_OK;
 }

@@ -395,10 +395,10 @@ void release_all()
     (void)sync_ended(st);
     recycle(st);
     for (hipEvent_t e : st.pool)
-        (void)hipEventDestroy(e);
+        RNGX_NOTE(hipEventDestroy(e));
     st.pool.clear();
     if (st.ref)
-        (void)hipEventDestroy(st.ref);
+        RNGX_NOTE(hipEventDestroy(st.ref));
     st.ref = nullptr;
     st.open = false;
     st.names.clear();

@@ -253,12 +253,17 @@ void spin_for(uint64_t ns)
 void worker_main(Server *sp)
 {
     Server &s = *sp;
-    (void)hipSetDevice(s.device);
+    const hipError_t dev_e = hipSetDevice(s.device);
     // Timed waits of this thread should not be stretched by the default
     // 50 us timer slack.
     (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0, 0, 0);
     std::vector<StageReq> items;
     std::unique_lock<std::mutex> lk(s.mu);
+    if (dev_e != hipSuccess) {
+        // Nothing can be launched from this thread: every waiter gets this.
+        s.worker_rc = hip_fail(dev_e, "serve: hipSetDevice (scheduler thread)");
+        s.worker_msg = rngx_last_error();
+    }
     const SeedMix mix = seed_mix(s.seed); // unused by the kernel: states are resident
     for (;;) {
         bool progress = false, busy = false;
@@ -532,10 +537,10 @@ void stop_locked(Server &s, std::unique_lock<std::mutex> &lk)
     s.flights.clear();
     for (hipStream_t st : s.streams)
         if (st)
-            (void)hipStreamDestroy(st);
+            RNGX_NOTE(hipStreamDestroy(st));
     s.streams.clear();
     if (s.d_states)
-        (void)hipFree(s.d_states);
+        RNGX_NOTE(hipFree(s.d_states));
     s.d_states = nullptr;
     s.reqs.clear(s.reqs.next_ticket()); // tickets stay unique across restarts
     s.pending.clear();
@@ -600,7 +605,7 @@ extern "C" int rngx_serve_start(uint64_t seed, uint32_t n_states, void *pool, ui
         // The resident base states: the init kernel, once.
         hipStream_t s0 = s.streams[0];
         const int tok = prof::begin("INIT_KERNEL", s0);
-        drop_pending_hip_error();
+        take_stray_error("before the serving init kernel launch");
         e = launch_init(s.d_states, n_states, seed_mix(seed), s0);
         prof::end(tok, s0);
         if (e == hipSuccess)
@@ -611,10 +616,10 @@ extern "C" int rngx_serve_start(uint64_t seed, uint32_t n_states, void *pool, ui
     if (rc) {
         for (hipStream_t st : s.streams)
             if (st)
-                (void)hipStreamDestroy(st);
+                RNGX_NOTE(hipStreamDestroy(st));
         s.streams.clear();
         s.flights.clear();
-        (void)hipFree(s.d_states);
+        RNGX_NOTE(hipFree(s.d_states));
         s.d_states = nullptr;
         return rc;
     }

@@ -115,6 +115,8 @@ _SIGS = {
     "rngx_shutdown": ([], _int),
     "rngx_last_error": ([], ctypes.c_char_p),
     "rngx_strerror": ([_int], ctypes.c_char_p),
+    "rngx_hip_notes": ([ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.c_char_p,
+                        ctypes.c_size_t, _int], _int),
     "rngx_set_launch": ([_int, ctypes.POINTER(Launch)], _int),
     "rngx_get_launch": ([_int, ctypes.POINTER(Launch)], _int),
     "rngx_stream_to_host": ([_u32, _u32, _int, _p, _p, ctypes.c_size_t, _p, _u32, CONSUME_FN,
@@ -177,6 +179,18 @@ def strerror(code: int) -> str:
 
 def last_error() -> str:
     return lib().rngx_last_error().decode()
+
+
+def hip_notes(clear: bool = False) -> dict:
+    """HIP errors no call could return: failures on the library's release
+    paths ("released") and errors found pending before a launch ("stray"),
+    with the most recent notes as text."""
+    rel, stray = _u64(), _u64()
+    buf = ctypes.create_string_buffer(8192)
+    _check(lib().rngx_hip_notes(ctypes.byref(rel), ctypes.byref(stray), buf, len(buf),
+                                int(bool(clear))))
+    return {"released": rel.value, "stray": stray.value,
+            "notes": [l for l in buf.value.decode().split("\n") if l]}
 
 
 def _check(rc: int):

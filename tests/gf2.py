@@ -96,3 +96,24 @@ def shift_xor_map(w, a, b, c):
         x ^= (x << c) & mask
         return x
     return f
+
+
+class Jumper:
+    """k steps of a GF(2)-linear step map on w-bit words, for any k < 2^w:
+    the matrices M^(2^b) are built once by repeated squaring of the step's
+    matrix (probed from the step function on unit vectors), and M^k x is
+    the product of those with b a set bit of k, applied one after another."""
+
+    def __init__(self, step, w=64):
+        self.pow2 = [from_linear_map(step, w)]
+        for _ in range(w - 1):
+            self.pow2.append(mul(self.pow2[-1], self.pow2[-1]))
+
+    def jump(self, x, k):
+        b = 0
+        while k:
+            if k & 1:
+                x = apply(self.pow2[b], x)
+            k >>= 1
+            b += 1
+        return x

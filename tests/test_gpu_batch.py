@@ -7,6 +7,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from paper_1609_01257_amd import inputs, rngx
+from tests import gf2, parity
 
 pytestmark = pytest.mark.gpu
 
@@ -97,11 +98,20 @@ def test_tiny_and_zero_length_requests(oracle):
         assert np.array_equal(_run(_reqs(r), r.total), exp)
 
 
-def test_huge_offsets_use_jump_ahead(oracle):
+@pytest.fixture(scope="module")
+def jumper(oracle):
+    # k oracle steps for any k: powers of the step's GF(2) matrix, probed
+    # from the oracle's own step function (independent of the library's
+    # jump tables).
+    return gf2.Jumper(oracle.rng_step)
+
+
+def test_huge_offsets_use_jump_ahead(oracle, jumper):
     # Offsets far beyond what stepping could reach; checked through the
-    # oracle's group law: value(s, g, k) = step applied k times, so compare the
-    # first value of each request with the host-side jump and the following
-    # values with sequential oracle steps from it.
+    # group law value(s, g, k) = M^k x0 with M the matrix of the oracle's
+    # step: the first value of each request is M^k applied to the oracle's
+    # initial state, and the checker continues from it with sequential
+    # oracle steps.
     rng = np.random.default_rng(17)
     m = 12
     offs = rng.integers(2**40, 2**63, m, dtype=np.uint64)
@@ -109,13 +119,11 @@ def test_huge_offsets_use_jump_ahead(oracle):
                         rng.integers(0, 2**32, m, dtype=np.uint64).astype(np.uint32),
                         offs, rng.integers(1, 3000, m).astype(np.uint64))
     got = _run(_reqs(r), r.total)
-    base = 0
-    for j in range(m):
-        x = rngx.jump_ahead(oracle.init_state(int(r.seeds[j]), int(r.gids[j])), int(offs[j]))
-        for t in range(int(r.lengths[j])):
-            assert int(got[base + t]) == x, (j, t)
-            x = oracle.rng_step(x)
-        base += int(r.lengths[j])
+    starts = np.array([jumper.jump(oracle.init_state(int(r.seeds[j]), int(r.gids[j])),
+                                   int(offs[j])) for j in range(m)], dtype=np.uint64)
+    bases = np.concatenate([[0], np.cumsum(r.lengths)[:-1]]).astype(np.uint64)
+    res = parity.check_requests(_oracle_reqs(oracle, r), got.ctypes.data, bases, starts=starts)
+    assert res["mismatches"] == 0, res
 
 
 def test_transpose_of_plain_output(oracle):
@@ -123,11 +131,7 @@ def test_transpose_of_plain_output(oracle):
     seed, n, iters = 77, 1000, 300
     r = rngx.make_reqs([seed] * n, np.arange(n), np.zeros(n), np.full(n, iters))
     got = _run(r, n * iters).reshape(n, iters)
-    rngx.init(seed, n)
-    plain = torch.empty(n * iters, dtype=torch.int64, device="cuda")
-    rngx.generate(iters, plain)
-    torch.cuda.synchronize()
-    assert np.array_equal(got.T, plain.cpu().numpy().view(np.uint64).reshape(iters, n))
+    assert np.array_equal(got.T, oracle.generate(seed, n, iters))
 
 
 def test_graph_replays_with_changing_tables(oracle):
@@ -200,41 +204,16 @@ def test_batch_errors_on_device():
     assert L.rngx_generate_batch(r.ctypes.data, 0, out.data_ptr(), 0, None) == rngx.RNGX_OK
 
 
-def test_batched_config_full_size_sampled(oracle):
-    """4,096 streams, seeds from default_rng(1609), lengths log-uniform in
-    [2^10, 2^24), one launch; 48 requests (plus the shortest and the longest)
-    compared in full with the oracle, and the checksum of the whole output
-    recomputed from a second launch for determinism."""
-    r = inputs.batched_requests()
-    out = torch.empty(r.total, dtype=torch.int64, device="cuda")
-    rngx.generate_batch(_reqs(r), out)
-    c1 = rngx.checksum(out, r.total)
-    starts = np.concatenate([[0], np.cumsum(r.lengths.astype(np.int64))])
-    rng = np.random.default_rng(4096)
-    pick = set(rng.choice(len(r), 48, replace=False).tolist())
-    pick |= {int(np.argmin(r.lengths)), int(np.argmax(r.lengths))}
-    for j in sorted(pick):
-        got = out[int(starts[j]):int(starts[j + 1])].cpu().numpy().view(np.uint64)
-        one = oracle.make_reqs([r.seeds[j]], [r.gids[j]], [0], [r.lengths[j]])
-        assert np.array_equal(got, oracle.generate_batch(one)), j
-    rngx.generate_batch(_reqs(r), out)
-    assert rngx.checksum(out, r.total) == c1
-    # The same table with one wave per item: same output.
-    rngx.set_batch_cfg(64, 4, 0, True, 16, 1, True)
-    out.zero_()
-    rngx.generate_batch(_reqs(r), out)
-    assert rngx.checksum(out, r.total) == c1
-    del out
-    torch.cuda.empty_cache()
-
-
-def test_last_value_numbers_of_a_stream(oracle):
+def test_last_value_numbers_of_a_stream(oracle, jumper):
     # A request may end exactly at value number 2^64 - 1; checked through the
-    # group law (value k+1 = one step from value k) from a host-side jump.
+    # group law (value k+1 = one step from value k) from M^k x0, M the
+    # matrix of the oracle's step. M^(2^64 - 1) is the identity (full
+    # period), so value number 2^64 - 1 is the initial state itself.
     r = rngx.make_reqs([5, 5], [3, 4], [2**64 - 6, 2**64 - 1], [6, 1])
     got = _run(r, 7)
+    assert int(got[6]) == oracle.init_state(5, 4)
     for j, (off, n, base) in enumerate([(2**64 - 6, 6, 0), (2**64 - 1, 1, 6)]):
-        x = rngx.jump_ahead(oracle.init_state(5, 3 + j), off)
+        x = jumper.jump(oracle.init_state(5, 3 + j), off)
         for t in range(n):
             assert int(got[base + t]) == x, (j, t)
             x = oracle.rng_step(x)

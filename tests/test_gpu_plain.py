@@ -223,32 +223,6 @@ def test_shutdown_releases_device_memory():
     assert abs(free2 - free0) < (64 << 20)
 
 
-def _sampled_check(oracle, seed, n, iters, u32, count=4096):
-    """Full-size run in the benchmark's launch configuration; compare a
-    uniform sample of positions (plus corners) with the oracle one by one."""
-    rngx.init(seed, n)
-    dt = torch.int32 if u32 else torch.int64
-    out = torch.empty(iters * n, dtype=dt, device="cuda")
-    (rngx.generate_u32 if u32 else rngx.generate)(iters, out)
-    k, g = inputs.sample_positions(n, iters, count, seed=seed)
-    idx = torch.from_numpy(k * n + g).to("cuda")
-    got = out.index_select(0, idx).cpu().numpy().view(np.uint32 if u32 else np.uint64)
-    del out
-    torch.cuda.empty_cache()
-    for j in range(len(k)):
-        v = oracle.value(seed, int(g[j]), int(k[j]))
-        if u32:
-            v &= 0xFFFFFFFF
-        assert int(got[j]) == v, (int(k[j]), int(g[j]))
-
-
-@pytest.mark.parametrize("n", inputs.ROOFLINE_N)
-def test_roofline_sizes_sampled(oracle, n):
-    seed = inputs.ROOFLINE_SEEDS[inputs.ROOFLINE_N.index(n)]
-    _sampled_check(oracle, seed, n, inputs.ROOFLINE_ITERS, u32=False)
-    _sampled_check(oracle, seed, n, inputs.ROOFLINE_ITERS, u32=True)
-
-
 def test_roofline_small_full(oracle):
     n, iters = 1 << 20, 16
     got = run(1, n, iters)

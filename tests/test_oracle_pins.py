@@ -361,3 +361,49 @@ def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
                    check=True)
     r = subprocess.run([exe], capture_output=True, text=True)
     assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
+
+
+# --- slice-at-a-time entries (gid ranges, continuation from a state array) ---
+
+@pytest.mark.parametrize("seed,cursor", [(0, 0), (42, 3), (2**64 - 1, 17)])
+def test_range_output_is_the_matching_columns(oracle, seed, cursor):
+    # generate_range(g0, g1) equals columns g0..g1 of generate, and the seeded
+    # states are value() one by one (value is pinned by the hand trace).
+    n, iters = 3000, 6
+    full = oracle.generate(seed, n, iters, cursor=cursor)
+    for g0, g1 in [(0, n), (0, 1), (1234, 2999), (2999, 3000), (700, 700)]:
+        assert np.array_equal(oracle.generate_range(seed, g0, g1, iters, cursor=cursor),
+                              full[:, g0:g1]), (g0, g1)
+    st = oracle.seed_range(seed, 5, 20, cursor)
+    assert [int(v) for v in st] == [oracle.value(seed, g, cursor) for g in range(5, 25)]
+
+
+def test_range_reaches_the_last_work_item(oracle):
+    # The top of the 32-bit gid space, where the range ends at 2^32.
+    top = 2**32
+    got = oracle.generate_range(9, top - 4, top, 3)
+    for j, g in enumerate(range(top - 4, top)):
+        assert [int(v) for v in got[:, j]] == [oracle.value(9, g, k) for k in range(3)]
+
+
+def test_continuation_concatenates(oracle):
+    # Rows emitted from a state array continue where the last call stopped:
+    # emit(a) then emit(b) equals emit(a + b), and the state array ends at the
+    # next value of every stream.
+    seed, n = 77, 513
+    st = oracle.seed_range(seed, 0, n, 0)
+    parts = [oracle.emit_rows(st, a) for a in (1, 4, 2)]
+    assert np.array_equal(np.vstack(parts), oracle.generate(seed, n, 7))
+    assert np.array_equal(st, oracle.generate(seed, n, 1, cursor=7)[0])
+
+
+def test_continuation_words(oracle):
+    # u32 rows are the low halves, scrambled rows the scrambled words of the
+    # same states, scrambled u32 rows their high halves.
+    seed, n, rows = 5, 301, 3
+    plain = oracle.generate(seed, n, rows)
+    for word, exp in [(oracle.WORD_U32, (plain & np.uint64(0xFFFFFFFF)).astype(np.uint32)),
+                      (oracle.WORD_STAR, oracle.generate_star(seed, n, rows)),
+                      (oracle.WORD_STAR_U32, oracle.generate_star_u32(seed, n, rows))]:
+        st = oracle.seed_range(seed, 0, n, 0)
+        assert np.array_equal(oracle.emit_rows(st, rows, word), exp), word
