@@ -41,8 +41,8 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.run(["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-fPIC", "-shared",
-                        "-pthread", "-o", tmp, _SRC, olib,
-                        "-Wl,-rpath,$ORIGIN/../../oracle"], check=True)
+                        "-pthread", "-o", tmp, _SRC, "-L", os.path.dirname(olib),
+                        "-l:liboracle.so", "-Wl,-rpath,$ORIGIN/../../oracle"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
