@@ -191,6 +191,18 @@ def batched(torch, rngx, steps):
     t1 = time.perf_counter()
     st = rngx.profile_stats()
     avg, count = kernel_avg_s(st, "BATCH_KERNEL")
+    # The persistent grid (S = 256, 8 waves per compute unit, runs of one
+    # item) on the same table, whatever the autotuner picked.
+    tuned = rngx.get_batch_cfg()
+    rngx.set_batch_cfg(256, 4, 0, True, 16, 1, False)
+    rngx.generate_batch(reqs, out)
+    torch.cuda.synchronize()
+    rngx.profile_start()
+    for _ in range(steps):
+        rngx.generate_batch(reqs, out)
+    torch.cuda.synchronize()
+    pavg, _ = kernel_avg_s(rngx.profile_stats(), "BATCH_KERNEL")
+    rngx.set_batch_cfg(**tuned)
     # The plain generator writing the batched output buffer itself (2^24
     # streams x floor(total / 2^24) iterations): same memory, so the ratio
     # does not depend on where either buffer landed in HBM.
@@ -213,6 +225,9 @@ def batched(torch, rngx, steps):
         "frac_hbm": round(nbytes / avg / 1e9 / HBM_PEAK_GBS, 4),
         "autotune_best": tune["best"],
         "autotune_candidates": len(tune["tried"]),
+        "persistent_s256": {"kernel_avg_ms": round(pavg * 1e3, 4),
+                            "kernel_gbs": round(nbytes / pavg / 1e9, 1),
+                            "frac_hbm": round(nbytes / pavg / 1e9 / HBM_PEAK_GBS, 4)},
         "plain_equal_bytes": {"n_states": n_eq, "iters": it_eq,
                               "kernel_gbs": round(plain["kernel_gbs"], 1),
                               "out_gbs": round(plain["out_gbs"], 1)},
@@ -229,7 +244,10 @@ def serving(torch, rngx, seconds, plain_gbs):
     admission, 4 streams, batches of up to 2,048 requests with at most 2 in
     flight, Poisson arrivals at 2k / 10k / 50k req/s (stream id uniform,
     length log-uniform in [2^12, 2^22)), results released on completion;
-    then a saturation run (a pre-filled backlog) for throughput."""
+    latency from each request's scheduled arrival to its completion. Then a
+    saturation run (a pre-filled backlog) for throughput, compared with the
+    batched kernel writing the same requests into the same pool without the
+    server (batches of the server's mean size, back to back)."""
     from paper_1609_01257_amd import inputs
     pool = torch.empty(16 * 10**9, dtype=torch.uint8, device="cuda")
     rngx.serve_start(1609, 1 << 20, pool, 4, 2048)
@@ -245,6 +263,8 @@ def serving(torch, rngx, seconds, plain_gbs):
                    "p50_us": round(st["lat_p50_us"], 1), "p99_us": round(st["lat_p99_us"], 1),
                    "max_us": round(st["lat_max_us"], 1),
                    "wait_p99_us": round(st["wait_p99_us"], 1),
+                   "submit_lag_p50_us": round(st["lag_p50_us"], 1),
+                   "submit_lag_p99_us": round(st["lag_p99_us"], 1),
                    "launch_p50_us": round(st["launch_p50_us"], 1),
                    "exec_p50_us": round(st["exec_p50_us"], 1),
                    "mean_batch": round(st["mean_batch_requests"], 2),
@@ -267,6 +287,44 @@ def serving(torch, rngx, seconds, plain_gbs):
                              "p99_us": round(st["lat_p99_us"], 1)}
         res["saturation"]["served_vs_plain"] = round(st["gbs"] / plain_gbs, 4)
         rngx.serve_stop()
+        # The same requests, in consecutive batches of the server's mean
+        # batch size, each written by the batched kernel into the pool in the
+        # schedule the server uses for large batches (persistent grid,
+        # S = 256): what the server would reach with no overhead of its own.
+        per = max(1, int(round(st["mean_batch_requests"])))
+        chunks = []
+        for a in range(0, len(L), per):
+            b = min(len(L), a + per)
+            while 8 * int(L[a:b].sum()) > pool.numel():
+                b -= 1
+            chunks.append(rngx.make_reqs(np.full(b - a, 1609, dtype=np.uint64), g[a:b],
+                                         np.zeros(b - a), L[a:b]))
+        words = pool.view(torch.int64)
+        # Each batch lands after the previous one, wrapping at the end of
+        # the pool, as the server's ring places them.
+        places, off = [], 0
+        for c in chunks:
+            size = int(c["length"].sum())
+            if off + size > words.numel():
+                off = 0
+            places.append(words[off:off + size])
+            off += (size + 1) & ~1       # keep every batch 16-byte aligned
+        tuned = rngx.get_batch_cfg()
+        rngx.set_batch_cfg(256, 4, 0, False, 16, 1, False)
+        try:
+            rngx.generate_batch(chunks[0], places[0])      # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c, dst in zip(chunks, places):
+                rngx.generate_batch(c, dst)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            rngx.set_batch_cfg(**tuned)
+        bip = 8 * float(L.sum()) / dt / 1e9
+        res["saturation"]["batched_in_pool_gbs"] = round(bip, 1)
+        res["saturation"]["batched_in_pool_batches"] = len(chunks)
+        res["saturation"]["served_vs_batched_in_pool"] = round(st["gbs"] / bip, 4)
         # The plain kernel writing the pool itself (2^22 states x 476
         # iterations = 15.97 GB per launch): the same memory the served
         # batches wrote, so the ratio does not depend on where either
@@ -284,24 +342,68 @@ def serving(torch, rngx, seconds, plain_gbs):
     return res
 
 
-def cpu_baseline(n_total, iters, min_seconds=10.0):
-    """The CPU oracle, single-threaded, on the first 2^20 work-items of the
-    workload (all iterations), repeated until at least `min_seconds` of CPU
-    work have been timed."""
+def host_description():
+    """CPU model, the oracle's compiler and flags (for the CPU baseline)."""
+    import subprocess
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        cc = subprocess.run(["gcc", "--version"], capture_output=True, text=True).stdout
+        cc = cc.splitlines()[0].strip()
+    except (OSError, IndexError):
+        cc = "gcc"
+    return {"cpu_model": model, "host_cpus": os.cpu_count(), "compiler": cc,
+            "flags": "-std=c99 -O2"}
+
+
+def cpu_baseline(n_total, iters, min_seconds=10.0, single_seconds=5.0):
+    """The CPU oracle (plain C, sequential definition) on a bounded sample of
+    the headline workload: T threads (the box's share of 16 cores, at most),
+    each computing a contiguous slice of 2^17 work-items for all iterations
+    with the oracle's gid-range entry, repeated until at least `min_seconds`
+    have passed; plus the same oracle on one thread."""
+    import concurrent.futures as cf
     import oracle
-    n = 1 << 20
-    calls, dt, nbytes = 0, 0.0, 0
-    while dt < min_seconds:
+    lib = oracle.lib()
+    threads = max(1, min(16, os.cpu_count() or 1))
+    per = 1 << 17
+    bufs = [np.empty(per * iters, dtype=np.uint64) for _ in range(threads)]
+
+    def one(t):
+        z = lib.oracle_generate_range(1, t * per, (t + 1) * per, 0, iters, bufs[t].ctypes.data)
+        if z:
+            raise AssertionError("oracle produced zero values")
+        return bufs[t].nbytes
+
+    nbytes, passes = 0, 0
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
         t0 = time.perf_counter()
-        out = oracle.generate(1, n, iters)
-        dt += time.perf_counter() - t0
-        nbytes += out.nbytes
-        calls += 1
-        del out
-    gbs = nbytes / dt / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d work-items x %d iterations (u64, %.1f GiB), computed "
-                      "%d times in %.1f s" % (n, n_total, iters, n * iters * 8 / GIB, calls, dt)}
+        while time.perf_counter() - t0 < min_seconds:
+            nbytes += sum(ex.map(one, range(threads)))
+            passes += 1
+        dt = time.perf_counter() - t0
+    mt = nbytes / dt / 1e9
+    n1, d1, b1 = 0, 0.0, 0
+    while d1 < single_seconds:
+        t1 = time.perf_counter()
+        b1 += one(0)
+        d1 += time.perf_counter() - t1
+        n1 += 1
+    del bufs
+    res = {"value": round(mt, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": "first %d of %d work-items x %d iterations (u64, %.1f GiB), one "
+                     "contiguous slice of %d work-items per thread, computed %d times in "
+                     "%.1f s" % (threads * per, n_total, iters, threads * per * iters * 8 / GIB,
+                                 per, passes, dt),
+           "single_thread_gbs": round(b1 / d1 / 1e9, 3)}
+    res.update(host_description())
+    return res
 
 
 def main():
@@ -311,8 +413,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-sweep", action="store_true", help="skip the size/dtype sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
-                    help="duration of each Poisson serving run (60 for the full runs)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="duration of each Poisson serving run")
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline kernel (for profiling)")
     ap.add_argument("--batched-only", action="store_true",
@@ -321,6 +423,9 @@ def main():
                     help="run only the paper-shaped streaming pipeline (for profiling)")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving runs (for profiling)")
+    ap.add_argument("--plain-shape", type=int, nargs=2, metavar=("N_STATES", "ITERS"),
+                    help="run only the plain generator at this shape (for profiling)")
+    ap.add_argument("--u32", action="store_true", help="with --plain-shape: 32-bit output")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 16 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--placement-probe", action="store_true",
@@ -372,6 +477,16 @@ def main():
             res.append({"buffer": i, "kernel_gbs": rates})
         rngx.shutdown()
         print(json.dumps({"placement_probe": res}), flush=True)
+        return
+    if args.plain_shape:
+        n_s, it_s = args.plain_shape
+        log("plain %s, n=%d, iters=%d" % ("u32" if args.u32 else "u64", n_s, it_s))
+        r = plain_run(torch, rngx, 1, n_s, it_s, args.u32, args.warmup, args.steps)
+        r["frac_hbm"] = r["kernel_gbs"] / HBM_PEAK_GBS
+        log("plain:", r)
+        rngx.shutdown()
+        print(json.dumps({"plain": r, "n_states": n_s, "iters": it_s, "u32": args.u32}),
+              flush=True)
         return
     if args.batched_only:
         rngx.init(1, 64)          # opens the profiling window the step is timed in

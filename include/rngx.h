@@ -415,6 +415,10 @@ typedef struct rngx_serve_report {
     uint64_t max_pending, admission_stalls;
     double mean_batch_requests;
     uint64_t pool_bytes, pool_used_bytes, pool_peak_bytes;
+    /* Requests of rngx_serve_run_trace only: submission lag, the time from a
+     * request's scheduled arrival to its actual submission (their latency
+     * above is measured from the scheduled arrival, so it includes this). */
+    double lag_p50_us, lag_p99_us, lag_max_us;
 } rngx_serve_report;
 
 int rngx_serve_stats(rngx_serve_report *out);
@@ -427,7 +431,11 @@ int rngx_serve_reset_stats(void);
  * form a backlog),
  * then wait until every request has completed
  * (at most timeout_s) and report the statistics of this trace (they are
- * reset at the start). Errors: as rngx_serve_submit; RNGX_E_BUSY on timeout. */
+ * reset at the start). A traced request's latency, admission wait and
+ * launch delay are measured from its scheduled arrival, not from its actual
+ * submission, so any lag of the submitting thread (for instance while the
+ * scheduler holds the server's lock) counts against them; the lag itself is
+ * reported as lag_*. Errors: as rngx_serve_submit; RNGX_E_BUSY on timeout. */
 int rngx_serve_run_trace(const double *arrival_s, const uint32_t *stream_id,
                          const uint64_t *length, uint64_t k, double timeout_s,
                          rngx_serve_report *out);

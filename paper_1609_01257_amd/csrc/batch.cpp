@@ -24,7 +24,9 @@ namespace {
 const uint32_t kValuesPerLane[7] = {16, 32, 64, 128, 256, 512, 1024};
 constexpr int kNumS = 7;
 
-int s_index(uint32_t s)
+} // namespace
+
+int batch_s_index(uint32_t s)
 {
     for (int i = 0; i < kNumS; ++i)
         if (kValuesPerLane[i] == s)
@@ -32,14 +34,25 @@ int s_index(uint32_t s)
     return -1;
 }
 
-// Device tables, one set per device that has launched a batch; kept until
-// rngx_shutdown, so work in flight on one device never loses its tables when
-// another device becomes current.
+// The constant tables every batch launch reads, in static device memory: one
+// copy per device, which lives as long as the process (942 KiB). They are
+// filled on a device's first batched call of any kind, so later calls, also
+// the allocation-free entry point, only enqueue work.
+__device__ __align__(256) uint64_t g_pow2[64 * 64];                  // T^(2^b), 64 rows each
+__device__ __align__(256) uint64_t g_spread[kNumS * kSpreadTable];   // lane-spread tables per S
+__device__ __align__(256) uint64_t g_carry_nib[kNumS * kCarryTable]; // T^(63 S) nibble tables per S
+
+namespace {
+
+// Per-device bookkeeping: the device addresses of the static tables once
+// they are filled there, and the checksum accumulator (allocated on the
+// first checksum, freed by rngx_shutdown).
 struct DevTables {
     int n_cus = 0;
-    uint64_t *d_pow2 = nullptr;      // 64 matrices x 64 rows
-    uint64_t *d_spread = nullptr;    // lane-spread tables for each allowed S (kNumS x kSpreadTable)
-    uint64_t *d_carry_nib = nullptr; // T^(63 S) nibble tables for each allowed S (kNumS x 256)
+    bool loaded = false;
+    const uint64_t *d_pow2 = nullptr;
+    const uint64_t *d_spread = nullptr;
+    const uint64_t *d_carry_nib = nullptr;
     uint64_t *d_acc = nullptr;       // checksum accumulator
     uint64_t *h_acc = nullptr;       // page-locked copy of it
 };
@@ -58,19 +71,15 @@ BatchGlobals &G()
     return *g;
 }
 
-void free_tables(DevTables &t)
+// Free the checksum accumulator (the static tables stay filled).
+void free_acc(DevTables &t)
 {
-    if (t.d_pow2)
-        RNGX_NOTE(hipFree(t.d_pow2));
-    if (t.d_spread)
-        RNGX_NOTE(hipFree(t.d_spread));
-    if (t.d_carry_nib)
-        RNGX_NOTE(hipFree(t.d_carry_nib));
     if (t.d_acc)
         RNGX_NOTE(hipFree(t.d_acc));
     if (t.h_acc)
         RNGX_NOTE(hipHostFree(t.h_acc));
-    t = DevTables();
+    t.d_acc = nullptr;
+    t.h_acc = nullptr;
 }
 
 // Host images of the lane-spread and carry tables for every allowed S.
@@ -135,14 +144,19 @@ void free_slot(BatchSlot &s)
     s = BatchSlot();
 }
 
+std::mutex &tables_mu()
+{
+    static std::mutex *m = new std::mutex;
+    return *m;
+}
+
 } // namespace
 
 int batch_tables_locked(const uint64_t **pow2, const uint64_t **spread_all, int *n_cus,
                         const uint64_t **carry_nib_all)
 {
     // Own lock: the server thread reaches here without the batch API lock.
-    static std::mutex tables_mu;
-    std::lock_guard<std::mutex> lk(tables_mu);
+    std::lock_guard<std::mutex> lk(tables_mu());
     BatchGlobals &g = G();
     int dev = -1;
     RNGX_HIP(hipGetDevice(&dev));
@@ -150,35 +164,33 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **spread_all, int 
         return set_error(RNGX_E_INVAL, "batch: device %d is beyond the %d the library supports",
                          dev, kMaxDevices);
     DevTables &t = g.dev[dev];
-    if (!t.d_pow2) {
+    if (!t.loaded) {
+        // Device addresses of this device's copies of the static tables
+        // (the arrays' names are host-side stand-ins), then their contents.
         std::vector<uint64_t> spread, nib;
         build_host_tables(spread, nib);
-        DevTables n;
-        hipError_t e = hipMalloc(&n.d_pow2, 64 * 64 * sizeof(uint64_t));
+        void *p2 = nullptr, *ps = nullptr, *pc = nullptr;
+        int cus = 0;
+        hipError_t e = hipGetSymbolAddress(&p2, HIP_SYMBOL(g_pow2));
         if (e == hipSuccess)
-            e = hipMalloc(&n.d_spread, spread.size() * sizeof(uint64_t));
+            e = hipGetSymbolAddress(&ps, HIP_SYMBOL(g_spread));
         if (e == hipSuccess)
-            e = hipMalloc(&n.d_carry_nib, nib.size() * sizeof(uint64_t));
+            e = hipGetSymbolAddress(&pc, HIP_SYMBOL(g_carry_nib));
         if (e == hipSuccess)
-            e = hipMalloc(&n.d_acc, sizeof(uint64_t));
+            e = hipMemcpy(p2, jump_tables(), sizeof g_pow2, hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipHostMalloc(&n.h_acc, sizeof(uint64_t), hipHostMallocDefault);
+            e = hipMemcpy(ps, spread.data(), sizeof g_spread, hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMemcpy(n.d_pow2, jump_tables(), 64 * 64 * sizeof(uint64_t),
-                          hipMemcpyHostToDevice);
+            e = hipMemcpy(pc, nib.data(), sizeof g_carry_nib, hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMemcpy(n.d_spread, spread.data(), spread.size() * sizeof(uint64_t),
-                          hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(n.d_carry_nib, nib.data(), nib.size() * sizeof(uint64_t),
-                          hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipDeviceGetAttribute(&n.n_cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) {
-            free_tables(n);
+            e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess)
             return hip_fail(e, "batch: device tables");
-        }
-        t = n;
+        t.d_pow2 = static_cast<const uint64_t *>(p2);
+        t.d_spread = static_cast<const uint64_t *>(ps);
+        t.d_carry_nib = static_cast<const uint64_t *>(pc);
+        t.n_cus = cus;
+        t.loaded = true;
     }
     if (pow2)
         *pow2 = t.d_pow2;
@@ -252,18 +264,8 @@ int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
     uint64_t n_items = 0;
     for (uint32_t j = 0; j < k; ++j) {
         const StageReq &q = items[j];
-        BatchReq &r = tab[j];
-        r.offset = q.offset;
-        r.length = q.length;
-        r.vbase = q.vbase;
-        r.item_begin = n_items;
-        r.first_tile = q.vbase / C;
-        r.gid = q.gid;
-        r.mix_low = q.mix.mix_low;
-        r.mix_high = q.mix.mix_high;
-        r.zero_fix = q.mix.zero_fix;
-        r.dst = q.dst;
-        n_items += (q.vbase + q.length - 1) / C - r.first_tile + 1;
+        n_items += make_record(tab[j], q.offset, q.length, q.vbase, n_items, q.gid, q.mix, q.dst,
+                               C);
     }
     std::memset(desc, 0, sizeof *desc);
     desc->reqs = reinterpret_cast<const BatchReq *>(static_cast<char *>(slot.devtab) +
@@ -276,8 +278,8 @@ int batch_stage_items(BatchSlot &slot, const StageReq *items, uint32_t k,
     return RNGX_OK;
 }
 
-int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out,
-                uint64_t out_cap, uint32_t values_per_lane, uint64_t *total_out)
+int batch_validate(const rngx_req *reqs, uint32_t m, const uint64_t *out, uint64_t out_cap,
+                   uint64_t *total_out)
 {
     if (m && !reqs)
         return set_error(RNGX_E_INVAL, "batch: reqs is NULL");
@@ -300,8 +302,15 @@ int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out
     if (total && (reinterpret_cast<uintptr_t>(out) & 15u))
         return set_error(RNGX_E_INVAL, "batch: out is not 16-byte aligned");
     *total_out = (uint64_t)total;
-    if (total == 0)
-        return RNGX_OK;
+    return RNGX_OK;
+}
+
+int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out,
+                uint64_t out_cap, uint32_t values_per_lane, uint64_t *total_out)
+{
+    int rc = batch_validate(reqs, m, out, out_cap, total_out);
+    if (rc || *total_out == 0)
+        return rc;
     // Packed layout: the virtual index of a value is its output index.
     std::vector<StageReq> items;
     items.reserve(m);
@@ -348,8 +357,8 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, bool star, hipSt
     }
     BatchTables tabs;
     tabs.pow2 = pow2;
-    tabs.spread = spread_all + (size_t)kSpreadTable * s_index(cfg.values_per_lane);
-    tabs.carry_nib = nib_all + kCarryTable * s_index(cfg.values_per_lane);
+    tabs.spread = spread_all + (size_t)kSpreadTable * batch_s_index(cfg.values_per_lane);
+    tabs.carry_nib = nib_all + kCarryTable * batch_s_index(cfg.values_per_lane);
     const BatchDesc *ddesc = static_cast<const BatchDesc *>(slot.devtab);
     const int tok = prof::begin(prof_name, stream);
     if (cfg.use_graph) {
@@ -421,16 +430,24 @@ void release_batch()
     BatchGlobals &g = G();
     std::lock_guard<std::mutex> lk(g.mu);
     free_slot(g.api_slot);
+    std::lock_guard<std::mutex> lt(tables_mu());
     int cur = -1;
     RNGX_NOTE(hipGetDevice(&cur));
     for (int d = 0; d < kMaxDevices; ++d) {
-        if (!g.dev[d].d_pow2)
+        if (!g.dev[d].d_acc && !g.dev[d].h_acc)
             continue;
         RNGX_NOTE(hipSetDevice(d));
-        free_tables(g.dev[d]);
+        free_acc(g.dev[d]);
     }
     if (cur >= 0)
         RNGX_NOTE(hipSetDevice(cur));
+}
+
+rngx_batch_cfg current_batch_cfg()
+{
+    BatchGlobals &g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    return g.cfg;
 }
 
 int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *result)
@@ -441,6 +458,22 @@ int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *r
     int dev = -1;
     RNGX_HIP(hipGetDevice(&dev));
     DevTables &t = G().dev[dev];
+    {
+        std::lock_guard<std::mutex> lt(tables_mu());
+        if (!t.d_acc) {
+            void *d = nullptr, *h = nullptr;
+            hipError_t e = hipMalloc(&d, sizeof(uint64_t));
+            if (e != hipSuccess)
+                return hip_fail(e, "checksum: hipMalloc (accumulator)");
+            e = hipHostMalloc(&h, sizeof(uint64_t), hipHostMallocDefault);
+            if (e != hipSuccess) {
+                RNGX_NOTE(hipFree(d));
+                return hip_fail(e, "checksum: hipHostMalloc (accumulator)");
+            }
+            t.d_acc = static_cast<uint64_t *>(d);
+            t.h_acc = static_cast<uint64_t *>(h);
+        }
+    }
     RNGX_HIP(hipMemsetAsync(t.d_acc, 0, sizeof(uint64_t), s));
     take_stray_error("before the checksum kernel launch");
     RNGX_HIP(launch_checksum(data, n, t.d_acc, s));

@@ -102,6 +102,25 @@ struct BatchReq {
 };
 static_assert(sizeof(BatchReq) == 64, "BatchReq layout");
 
+// Fill one request record for tiles of C values; returns the number of work
+// items (tiles) the request touches.
+inline uint64_t make_record(BatchReq &r, uint64_t offset, uint64_t length, uint64_t vbase,
+                            uint64_t item_begin, uint32_t gid, const SeedMix &mix, uint64_t *dst,
+                            uint64_t C)
+{
+    r.offset = offset;
+    r.length = length;
+    r.vbase = vbase;
+    r.item_begin = item_begin;
+    r.first_tile = vbase / C;
+    r.gid = gid;
+    r.mix_low = mix.mix_low;
+    r.mix_high = mix.mix_high;
+    r.zero_fix = mix.zero_fix;
+    r.dst = dst;
+    return (vbase + length - 1) / C - r.first_tile + 1;
+}
+
 // Launch descriptor, read by the kernel from device memory so a captured
 // graph can be replayed with new contents. With `states` set, a request's
 // stream starts from states[gid] (resident states) instead of H(seed, gid).
@@ -148,6 +167,8 @@ struct BatchSlot {
 };
 
 bool batch_cfg_valid(const rngx_batch_cfg &c);
+// Index of an allowed values-per-lane S in the per-S tables.
+int batch_s_index(uint32_t s);
 // Entries of the per-S carry table: 16 nibble positions x 16 values.
 constexpr int kCarryTable = 256;
 // Entries of the per-S lane-spread table: 16 nibble positions x 16 values x
@@ -163,6 +184,9 @@ struct BatchTables {
 int batch_tables_locked(const uint64_t **pow2, const uint64_t **spread_all, int *n_cus,
                         const uint64_t **carry_nib_all = nullptr);
 rngx_batch_cfg resolved_cfg(const rngx_batch_cfg &c, int n_cus);
+// Argument checks of a batched call; *total_out = the values requested.
+int batch_validate(const rngx_req *reqs, uint32_t m, const uint64_t *out, uint64_t out_cap,
+                   uint64_t *total_out);
 int batch_stage(BatchSlot &slot, const rngx_req *reqs, uint32_t m, uint64_t *out,
                 uint64_t out_cap, uint32_t values_per_lane, uint64_t *total_out);
 // One request as staged by a host-side producer (the batch API or the server).
@@ -184,6 +208,8 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg, bool star, hipStrea
 int current_scrambler();
 void release_slot(BatchSlot &slot);
 void release_batch();
+// The batch API's launch configuration (rngx_set_batch_cfg / the autotuner).
+rngx_batch_cfg current_batch_cfg();
 void release_server(); // serve.cpp: stop the server, free its resources
 int checksum_locked(const uint64_t *data, uint64_t n, hipStream_t s, uint64_t *result);
 hipError_t launch_batch(const rngx_batch_cfg &cfg, const BatchDesc *desc, const BatchTables &t,

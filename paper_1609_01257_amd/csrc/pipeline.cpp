@@ -18,6 +18,7 @@
 // order once its copy is complete, and a host slot is reused only after the
 // consumer has returned for the step it held (host-side multi-buffering, the
 // paper's suggested improvement in Section 5).
+#include <algorithm>
 #include <vector>
 
 #include "internal.h"
@@ -44,12 +45,40 @@ void release_pipeline_locked(Generator &g)
 
 namespace {
 
+// A stream on a hardware queue of its own. HIP maps streams onto a small
+// pool of hardware queues (four per process by default); once the pool is
+// full, a new stream shares the least-used queue, and two streams on one
+// queue run their work in submission order. The pipeline's two streams,
+// created after the library's and the caller's other streams, could then
+// share a queue, and the kernel of step k + 1 would wait behind the copy of
+// step k: no overlap at all. A stream created with a compute-unit mask
+// always gets a queue of its own; the mask here enables every compute unit.
+// (Such a stream synchronises with the null stream like a default stream.)
+int create_own_queue_stream(hipStream_t *s)
+{
+    int dev = -1, cus = 0;
+    RNGX_HIP(hipGetDevice(&dev));
+    RNGX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    uint32_t mask[32];
+    const uint32_t words = (uint32_t)std::min(32, std::max(1, (cus + 31) / 32));
+    for (uint32_t i = 0; i < words; ++i)
+        mask[i] = 0xffffffffu;
+    RNGX_HIP(hipExtStreamCreateWithCUMask(s, words, mask));
+    return RNGX_OK;
+}
+
 int ensure_pipeline_locked(Generator &g)
 {
-    if (!g.pipe_gen)
-        RNGX_HIP(hipStreamCreateWithFlags(&g.pipe_gen, hipStreamNonBlocking));
-    if (!g.pipe_copy)
-        RNGX_HIP(hipStreamCreateWithFlags(&g.pipe_copy, hipStreamNonBlocking));
+    if (!g.pipe_gen) {
+        int rc = create_own_queue_stream(&g.pipe_gen);
+        if (rc)
+            return rc;
+    }
+    if (!g.pipe_copy) {
+        int rc = create_own_queue_stream(&g.pipe_copy);
+        if (rc)
+            return rc;
+    }
     for (int i = 0; i < 2; ++i) {
         if (!g.copy_done[i])
             RNGX_HIP(hipEventCreateWithFlags(&g.copy_done[i], hipEventDisableTiming));

@@ -102,7 +102,7 @@ struct Server {
     std::string worker_msg;
     std::atomic<uint64_t> submit_seq{0}; // bumped by every submission (lock-free peek)
     // statistics
-    std::vector<uint64_t> lat_ns, wait_ns, launch_ns, exec_ns;
+    std::vector<uint64_t> lat_ns, wait_ns, launch_ns, exec_ns, lag_ns;
     uint64_t submitted = 0, completed = 0, released = 0, batches = 0, batch_reqs = 0;
     uint64_t bytes_done = 0, t_first = 0, t_last = 0, max_pending_seen = 0, stalls = 0;
     bool stalled = false;
@@ -360,6 +360,7 @@ void reset_stats_locked(Server &s)
     s.wait_ns.clear();
     s.launch_ns.clear();
     s.exec_ns.clear();
+    s.lag_ns.clear();
     s.submitted = s.completed = s.released = s.batches = s.batch_reqs = 0;
     s.bytes_done = s.t_first = s.t_last = s.max_pending_seen = s.stalls = 0;
     s.stalled = false;
@@ -410,6 +411,10 @@ void fill_stats_locked(Server &s, rngx_serve_report *o)
     o->pool_bytes = s.pool_bytes;
     o->pool_used_bytes = s.alloc.used();
     o->pool_peak_bytes = s.alloc.peak();
+    std::vector<uint64_t> lag = s.lag_ns;
+    o->lag_p50_us = pct(lag, 50.0);
+    o->lag_p99_us = pct(lag, 99.0);
+    o->lag_max_us = lag.empty() ? 0.0 : *std::max_element(lag.begin(), lag.end()) * 1e-3;
 }
 
 int check_request_locked(Server &s, uint32_t stream_id, uint64_t length, uint32_t flags)
@@ -456,7 +461,9 @@ int make_room_locked(Server &s, std::unique_lock<std::mutex> &lk, bool wait)
     return RNGX_OK;
 }
 
-uint64_t enqueue_locked(Server &s, uint32_t stream_id, uint64_t length, uint32_t flags)
+// t_sched: the request's scheduled arrival (0: now, i.e. its submission).
+uint64_t enqueue_locked(Server &s, uint32_t stream_id, uint64_t length, uint32_t flags,
+                        uint64_t t_sched = 0)
 {
     SReq r;
     r.gid = stream_id;
@@ -464,7 +471,14 @@ uint64_t enqueue_locked(Server &s, uint32_t stream_id, uint64_t length, uint32_t
     r.autorelease = (flags & RNGX_SERVE_AUTORELEASE) != 0;
     r.offset = s.cursor[stream_id];
     r.length = length;
-    r.t_arrive = now_ns();
+    const uint64_t t_now = now_ns();
+    r.t_arrive = t_now;
+    if (t_sched) {
+        // Latency counts from the scheduled arrival; the submitter's delay
+        // is recorded on its own.
+        r.t_arrive = std::min(t_sched, t_now);
+        s.lag_ns.push_back(t_now - r.t_arrive);
+    }
     r.t_admit = r.t_launch = r.t_done = 0;
     r.pool_off = r.pool_seq = 0;
     r.live = true;
@@ -496,9 +510,10 @@ int submit_impl(uint32_t stream_id, uint64_t length, uint32_t flags, uint64_t *t
     return RNGX_OK;
 }
 
-// Submit k requests under one lock acquisition (tickets optional).
+// Submit k requests under one lock acquisition (tickets and scheduled
+// arrival times optional).
 int submit_many_impl(const uint32_t *ids, const uint64_t *lengths, uint64_t k, uint32_t flags,
-                     uint64_t *tickets)
+                     uint64_t *tickets, const uint64_t *t_sched = nullptr)
 {
     Server &s = SV();
     std::unique_lock<std::mutex> lk(s.mu);
@@ -510,7 +525,8 @@ int submit_many_impl(const uint32_t *ids, const uint64_t *lengths, uint64_t k, u
             rc = make_room_locked(s, lk, true);
         if (rc)
             break;
-        const uint64_t tk = enqueue_locked(s, ids[i], lengths[i], flags);
+        const uint64_t tk = enqueue_locked(s, ids[i], lengths[i], flags,
+                                           t_sched ? t_sched[i] : 0);
         if (tickets)
             tickets[i] = tk;
     }
@@ -772,10 +788,14 @@ extern "C" int rngx_serve_run_trace(const double *arrival_s, const uint32_t *str
             return set_error(RNGX_E_NOINIT, "serve: the server is not running");
         reset_stats_locked(s);
     }
+    // Scheduled arrival of every request, on the clock the server stamps with.
+    std::vector<uint64_t> sched(k);
     const uint64_t t0 = now_ns();
+    for (uint64_t i = 0; i < k; ++i)
+        sched[i] = t0 + (uint64_t)(arrival_s[i] * 1e9);
     uint64_t i = 0;
     while (i < k) {
-        const uint64_t due = t0 + (uint64_t)(arrival_s[i] * 1e9);
+        const uint64_t due = sched[i];
         uint64_t t = now_ns();
         while (t < due) {
             __builtin_ia32_pause();
@@ -785,10 +805,10 @@ extern "C" int rngx_serve_run_trace(const double *arrival_s, const uint32_t *str
         // chunks of at most 512 so that the scheduler can start launching
         // while a large backlog is still being submitted.
         uint64_t j = i + 1;
-        while (j < k && j - i < 512 && t0 + (uint64_t)(arrival_s[j] * 1e9) <= t)
+        while (j < k && j - i < 512 && sched[j] <= t)
             ++j;
         const int rc = submit_many_impl(stream_id + i, length + i, j - i, RNGX_SERVE_AUTORELEASE,
-                                        nullptr);
+                                        nullptr, sched.data() + i);
         if (rc)
             return rc;
         i = j;

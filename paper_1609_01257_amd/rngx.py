@@ -68,7 +68,9 @@ class ServeReport(ctypes.Structure):
                                                 "exec_p50_us", "exec_p99_us")] + \
                [("max_pending", ctypes.c_uint64), ("admission_stalls", ctypes.c_uint64),
                 ("mean_batch_requests", ctypes.c_double), ("pool_bytes", ctypes.c_uint64),
-                ("pool_used_bytes", ctypes.c_uint64), ("pool_peak_bytes", ctypes.c_uint64)]
+                ("pool_used_bytes", ctypes.c_uint64), ("pool_peak_bytes", ctypes.c_uint64),
+                ("lag_p50_us", ctypes.c_double), ("lag_p99_us", ctypes.c_double),
+                ("lag_max_us", ctypes.c_double)]
 
 
 class Launch(ctypes.Structure):

@@ -7,8 +7,8 @@ element by element with the CPU oracle.
   variant at the headline shape.
 - Batched: the 4,096-stream table (58.7 GB) in the default, autotuned,
   persistent and one-wave-per-item launch schedules, request by request.
-- Streaming: all 2,000 steps of 32 MiB of the paper-shaped pipeline, each
-  step compared as the consumer receives it.
+- Streaming: all 2,000 steps of 32 MiB of the paper-shaped pipeline, in
+  both copy modes, are compared in tests/test_gpu_stream.py.
 - Serving: two seconds of the 50k req/s Poisson trace; every request's
   device checksum served in the mix equals the one served alone, and the
   first 2,000 requests are compared in full with the oracle.
@@ -133,32 +133,6 @@ def test_batched_table_full(batched_table, schedule):
         _free()
     assert res["mismatches"] == 0, res
     assert res["values"] == r.total
-
-
-def test_streaming_every_step_full(oracle):
-    cfg = inputs.STREAMING
-    n, steps, seed = cfg["n"], cfg["iters"], cfg["seed"]
-    _say("streaming %d steps of %d values" % (steps, n))
-    st = parity.seed_states(seed, n)
-    dev0 = torch.empty(n, dtype=torch.int64, device="cuda")
-    dev1 = torch.empty(n, dtype=torch.int64, device="cuda")
-    host = torch.empty(2 * n, dtype=torch.int64, pin_memory=True)
-    rngx.init(seed, n)
-    seen, bad = [], []
-
-    def consume(step, arr):
-        res = parity.check_rows_ptr(arr.ctypes.data, n, n, 1, st, parity.WORD_U64)
-        seen.append(step)
-        if res["mismatches"]:
-            bad.append((step, res))
-            return True
-        return False
-    rngx.stream_to_host(steps, 1, dev0, dev1, host, 2, consume=consume)
-    rngx.shutdown()
-    del dev0, dev1, host
-    _free()
-    assert not bad, bad[:3]
-    assert seen == list(range(steps))
 
 
 def test_serving_trace_alone_vs_mix_and_oracle(oracle):

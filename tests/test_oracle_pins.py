@@ -407,3 +407,20 @@ def test_continuation_words(oracle):
                       (oracle.WORD_STAR_U32, oracle.generate_star_u32(seed, n, rows))]:
         st = oracle.seed_range(seed, 0, n, 0)
         assert np.array_equal(oracle.emit_rows(st, rows, word), exp), word
+
+
+def test_gf2_jumper_follows_the_oracle_step(oracle):
+    # The GPU tests' expected values for offsets no stepping could reach come
+    # from powers of the oracle step's GF(2) matrix. Pinned here against the
+    # oracle's sequential stepping for small k, the group law, and the full
+    # period (M^(2^64 - 1) = I).
+    J = gf2.Jumper(oracle.rng_step)
+    rng = np.random.default_rng(64)
+    for _ in range(6):
+        seed, g = int(rng.integers(0, 2**63)), int(rng.integers(0, 2**32))
+        k = int(rng.integers(0, 3000))
+        x0 = oracle.init_state(seed, g)
+        assert J.jump(x0, k) == oracle.value(seed, g, k)
+        a, b = int(rng.integers(0, 2**63)), int(rng.integers(0, 2**63))
+        assert J.jump(J.jump(x0, a), b) == J.jump(x0, a + b)
+        assert J.jump(x0, 2**64 - 1) == x0
