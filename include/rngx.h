@@ -226,6 +226,20 @@ int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, int u32, void
                         rngx_consume_fn consume, void *user, void *gen_stream,
                         void *copy_stream);
 
+/* Test hook for the pipeline's error path. In the paper's example a failed
+ * read ends the communications thread, which first wakes the main thread;
+ * the main thread then sees the error and stops (Section 5; supplementary
+ * Listings S1 and S2). Here, in the next rngx_stream_to_host call, the copy
+ * of step `step` fails before it is enqueued: the call waits for everything
+ * it already enqueued on both streams, calls the consumer for no further
+ * step, and returns RNGX_E_HIP with a message naming the step. Steps up to
+ * and including `step` have been generated (the cursor has advanced past
+ * them); the consumer has received the steps whose slots were already
+ * recycled. The hook fires once; UINT64_MAX disarms it. Nothing fails on the
+ * device: no kernel is launched for the failing copy.
+ * Errors: none. */
+int rngx_inject_copy_failure(uint64_t step);
+
 /* How rngx_stream_to_host moves each step to the host:
  * RNGX_COPY_KERNEL (default): the library's copy kernel stores straight into
  *   the page-locked host buffer through its device-mapped address (falls
@@ -317,16 +331,66 @@ typedef struct rngx_tune_result {
 } rngx_tune_result;
 
 /* Autotuner (the paper's work-size suggestion, Section 6.1, made empirical):
- * time every candidate launch configuration (values_per_lane 64..512 x
- * waves_per_block x [persistent: run_items 1 or 8 x waves per compute unit,
- * those whose LDS fits | one wave per item], 16-value rows) on this
- * request table with HIP events, check
+ * time every candidate configuration of the persistent launch
+ * (values_per_lane 64..512 x waves_per_block 2 or 4 x run_items 1 or 8 x
+ * 8, 16 or 32 waves per compute unit, those whose LDS fits; 16-value rows)
+ * on this request table with HIP events, check
  * that every candidate's output has the same checksum, keep the fastest as
  * the batch configuration, and report all of them. `out` receives the
  * requests' output. reps: timed launches per candidate (>= 1).
  * Errors: as rngx_generate_batch; RNGX_E_HIP if two candidates disagree. */
 int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_t out_cap,
                         uint32_t reps, void *stream, rngx_tune_result *result);
+
+/* Autotuner of the plain generator's launch configuration (the batched
+ * autotuner's counterpart, for rngx_generate / rngx_generate_u32): time
+ * every configuration block {256, 512, 1024} x chunks {1, 2, 4} x
+ * nontemporal {0, 1} on the current generator (its n_states) for n_iters
+ * iterations on `stream`, with HIP events around each launch; every
+ * candidate starts from a snapshot of the states, so all of them write the
+ * same values, V(seed, g, cursor + k) for k < n_iters, which is checked by
+ * checksum. The fastest becomes the launch configuration of that output type
+ * (as rngx_set_launch would set it). On return `out` holds those values and
+ * the generator's states and cursor are as before the call.
+ * out: device memory of n_iters * n_states values (8-byte, or 4-byte with
+ * u32, aligned). reps: timed launches per candidate (>= 1). The snapshot
+ * (8 * n_states bytes) is allocated and freed by the call.
+ * Errors: RNGX_E_NOINIT; RNGX_E_INVAL (NULL result or out, misaligned out,
+ * reps or n_iters 0); RNGX_E_NOMEM; RNGX_E_HIP (also when two candidates
+ * disagree). */
+typedef struct rngx_plain_tune_entry {
+    rngx_launch cfg;
+    double ms; /* mean kernel time over the timed launches */
+} rngx_plain_tune_entry;
+typedef struct rngx_plain_tune_result {
+    rngx_launch best;
+    double best_ms;
+    double best_gbs; /* algorithmic bytes (output + 16 per state) / best_ms */
+    uint32_t n_tried;
+    uint32_t reserved;
+    rngx_plain_tune_entry tried[RNGX_TUNE_MAX];
+} rngx_plain_tune_result;
+int rngx_autotune_plain(uint32_t n_iters, int u32, void *out, uint32_t reps, void *stream,
+                        rngx_plain_tune_result *result);
+
+/* Tuning cache: the chosen launch configurations kept across processes, one
+ * JSON object per line, keyed by device (architecture name and compute-unit
+ * count) and kind ("plain_u64", "plain_u32", "batch"), with the shape it was
+ * tuned on and its time.
+ * rngx_tune_cache_save: write the current device's three configurations
+ *   (rngx_get_launch for u64 and u32, rngx_get_batch_cfg) into `path`,
+ *   replacing that device's earlier entries and keeping every other line.
+ * rngx_tune_cache_load: apply the entries recorded for the current device
+ *   (as rngx_set_launch / rngx_set_batch_cfg); *applied (may be NULL) gets
+ *   their number. Entries of other devices are ignored.
+ * With the environment variable RNGX_TUNE_CACHE naming a file, the first
+ * successful rngx_init of the process loads it (if it exists), and each
+ * autotuner (rngx_autotune_plain, rngx_autotune_batch) records its choice
+ * there.
+ * Errors: RNGX_E_INVAL (NULL path, a file that cannot be read or written, a
+ * line that is not a tuning entry, an invalid configuration); RNGX_E_HIP. */
+int rngx_tune_cache_save(const char *path);
+int rngx_tune_cache_load(const char *path, uint32_t *applied);
 
 /* Order-sensitive checksum sum_i data[i] * (2 i + 1) mod 2^64 of n device
  * values, computed on the device; waits for `stream` and writes *result.

@@ -227,6 +227,14 @@ int rngx_init(uint64_t seed, uint32_t n_states)
     clear_error();
     if (n_states == 0)
         return set_error(RNGX_E_INVAL, "rngx_init: n_states must be at least 1");
+    // Once per process: the tuning cache named by RNGX_TUNE_CACHE.
+    static bool cache_applied = false;
+    if (!cache_applied) {
+        int rc = tune_cache_apply_env();
+        if (rc)
+            return rc;
+        cache_applied = true;
+    }
     int rc = fresh_state_locked(c, n_states, "rngx_init");
     if (rc)
         return rc;

@@ -376,7 +376,12 @@ int batch_launch(BatchSlot &slot, const rngx_batch_cfg &cfg_in, bool star, hipSt
             if (!slot.cap_stream)
                 RNGX_HIP(hipStreamCreateWithFlags(&slot.cap_stream, hipStreamNonBlocking));
             const size_t bytes = kReqOffset + (size_t)slot.capacity * sizeof(BatchReq);
-            RNGX_HIP(hipStreamBeginCapture(slot.cap_stream, hipStreamCaptureModeThreadLocal));
+            // Relaxed mode: a capture the library opens must never make a
+            // HIP call of another thread (a server's scheduler, the
+            // application's allocator) fail as unsafe during capture. The
+            // window holds only the table copy and the launch, which every
+            // mode allows.
+            RNGX_HIP(hipStreamBeginCapture(slot.cap_stream, hipStreamCaptureModeRelaxed));
             hipError_t e1 = hipMemcpyAsync(slot.devtab, slot.staging, bytes,
                                            hipMemcpyHostToDevice, slot.cap_stream);
             // (e1 is consumed here if it failed: it is reported below.)
@@ -573,25 +578,24 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
     uint64_t ref_sum = 0, total = 0;
     bool have_ref = false;
     double best = 1e300;
+    // The persistent launch (one grid that takes work items from a counter):
     // values_per_lane x run length x waves_per_block x waves per compute
     // unit, all with 128-byte rows (64-byte rows write half cache lines and
     // were much slower in every measurement); combinations whose LDS would
-    // not fit the waves per CU are skipped.
+    // not fit the waves per CU are skipped. One wave per item is not a
+    // candidate: it is a configuration of its own (rngx_set_batch_cfg) and
+    // the server's schedule for small batches.
     const uint32_t svals[4] = {64, 128, 256, 512};
     const uint32_t runs[2] = {1, 8};
     const uint32_t wpbs[2] = {2, 4};
     const uint32_t waves_per_cu[3] = {8, 16, 32};
     const uint32_t row = 16;
-    // Persistent candidates, then one wave per item (runs and waves per CU
-    // do not apply there: ui = 2 marks those, once per S and block size).
     for (uint32_t si = 0; si < 4; ++si) {
-      for (uint32_t ui = 0; ui < 3; ++ui) {
+      for (uint32_t ui = 0; ui < 2; ++ui) {
         for (uint32_t wi = 0; wi < 2; ++wi) {
             for (uint32_t oi = 0; oi < 3; ++oi) {
-                const bool per_item = ui == 2;
                 const uint32_t lds_per_block = 8u * (kCarryTable + wpbs[wi] * 64u * (row + 2));
-                if (per_item ? oi > 0
-                             : waves_per_cu[oi] / wpbs[wi] * lds_per_block > 160u * 1024u)
+                if (waves_per_cu[oi] / wpbs[wi] * lds_per_block > 160u * 1024u)
                     continue;
                 rngx_batch_cfg c;
                 c.values_per_lane = svals[si];
@@ -599,8 +603,8 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
                 c.blocks = (uint32_t)std::max(1, n_cus * (int)waves_per_cu[oi] / (int)wpbs[wi]);
                 c.use_graph = g.cfg.use_graph;
                 c.row_values = row;
-                c.run_items = per_item ? 1 : runs[ui];
-                c.per_item = per_item ? 1 : 0;
+                c.run_items = runs[ui];
+                c.per_item = 0;
                 rc = batch_stage(g.api_slot, reqs, m, out, out_cap, c.values_per_lane, &total);
                 if (rc)
                     return rc;
@@ -649,5 +653,5 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
     result->best_ms = best;
     result->best_gbs = (double)total * 8.0 / (best * 1e-3) / 1e9;
     g.cfg = result->best;
-    return RNGX_OK;
+    return tune_cache_record_batch(g.cfg, best, m, total);
 }

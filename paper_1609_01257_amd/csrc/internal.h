@@ -219,6 +219,11 @@ hipError_t launch_batch_small(const rngx_batch_cfg &cfg, const SmallTable &tab,
 // Checksum sum_i data[i] * (2 i + 1) mod 2^64 into *acc (device, pre-zeroed).
 hipError_t launch_checksum(const uint64_t *data, uint64_t n, uint64_t *acc, hipStream_t s);
 
+// tune.cpp: record the batched autotuner's choice in the cache named by
+// RNGX_TUNE_CACHE (no-op without it); apply that cache (once, at init).
+int tune_cache_record_batch(const rngx_batch_cfg &cfg, double ms, uint32_t m, uint64_t values);
+int tune_cache_apply_env();
+
 // jump.cpp: host GF(2) tables (64 matrices T^(2^b), 64 rows each).
 const uint64_t *jump_tables();
 uint64_t jump_host(uint64_t x, uint64_t k);
@@ -268,6 +273,9 @@ struct Generator {
     // 16 workgroups saturate PCIe 5.0 x16 on MI355X and slow the overlapping
     // generation kernel least (measured: 16 to 256 all within 4 %).
     uint32_t copy_blocks = 16;
+    // rngx_inject_copy_failure: step of the next streamed run whose copy
+    // fails (UINT64_MAX: none).
+    uint64_t fail_copy_at = UINT64_MAX;
 };
 
 Generator &generator();

@@ -125,6 +125,15 @@ extern "C" int rngx_get_copy_mode(int *mode, uint32_t *blocks)
     return RNGX_OK;
 }
 
+extern "C" int rngx_inject_copy_failure(uint64_t step)
+{
+    Generator &g = generator();
+    std::lock_guard<std::recursive_mutex> lk(g.mu);
+    clear_error();
+    g.fail_copy_at = step;
+    return RNGX_OK;
+}
+
 extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, int u32,
                                    void *dev0, void *dev1, size_t dev_bytes, void *host,
                                    uint32_t host_slots, rngx_consume_fn consume, void *user,
@@ -155,6 +164,9 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
     const size_t step_bytes = (size_t)step_bytes128;
     if ((unsigned __int128)step_bytes * host_slots > (unsigned __int128)SIZE_MAX)
         return set_error(RNGX_E_INVAL, "stream_to_host: host buffer size overflows size_t");
+    // The test hook applies to this call only.
+    const uint64_t fail_at = g.fail_copy_at;
+    g.fail_copy_at = UINT64_MAX;
     int rc = check_device_locked(g);
     if (rc)
         return rc;
@@ -236,6 +248,16 @@ extern "C" int rngx_stream_to_host(uint32_t n_steps, uint32_t iters_per_step, in
         // generate_locked recorded state_ready on gs right after the kernel:
         // it marks the generation's end, so no event of our own is queued.
         PIPE_HIP(hipStreamWaitEvent(cs, g.state_ready, 0));
+        if (k == fail_at) {
+            // Test hook: this step's copy "fails" before it is enqueued, as
+            // a read error in the paper's communications thread would.
+            const int code = set_error(RNGX_E_HIP,
+                                       "stream_to_host: device-to-host copy of step %llu failed "
+                                       "(forced by rngx_inject_copy_failure)",
+                                       (unsigned long long)k);
+            drain();
+            return code;
+        }
         const int tok = prof::begin("READ_BUFFER", cs);
         take_stray_error("before the device-to-host copy");
         hipError_t e = hmapped

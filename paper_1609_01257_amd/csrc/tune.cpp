@@ -1,0 +1,431 @@
+// The plain generator's autotuner and the persisted tuning cache.
+//
+// The paper suggests work sizes from device limits (Section 6.1); here the
+// launch configuration of the plain kernel is chosen by timing every
+// candidate on the caller's shape, as the batched path's autotuner does for
+// its kernel. Every candidate must produce the same output (checked by the
+// device checksum), so the choice never changes a value, only the time.
+//
+// The cache keeps the chosen configurations across processes: one line of
+// JSON per (device, kind), kind = plain_u64, plain_u32 or batch. Lines are
+// written by this file only, in a fixed key order, and read back with a
+// small key lookup; any line that does not parse is an error naming it.
+#include <cerrno>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace rngx {
+namespace {
+
+// "gfx950:sramecc+:xnack- 256cu": architecture and compute units of the
+// current device (a tuned choice belongs to both).
+int device_signature(std::string *sig)
+{
+    int dev = -1;
+    RNGX_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t p;
+    RNGX_HIP(hipGetDeviceProperties(&p, dev));
+    char buf[320];
+    std::snprintf(buf, sizeof buf, "%s %dcu", p.gcnArchName, p.multiProcessorCount);
+    *sig = buf;
+    return RNGX_OK;
+}
+
+struct CacheLine {
+    std::string device, kind, tuned_on;
+    uint32_t v[7] = {0, 0, 0, 0, 0, 0, 0};
+    double ms = 0.0;
+};
+
+const char *const kPlainKeys[3] = {"block", "chunks", "nontemporal"};
+const char *const kBatchKeys[7] = {"values_per_lane", "waves_per_block", "blocks", "use_graph",
+                                   "row_values", "run_items", "per_item"};
+
+int n_keys(const std::string &kind) { return kind == "batch" ? 7 : 3; }
+const char *const *keys_of(const std::string &kind)
+{
+    return kind == "batch" ? kBatchKeys : kPlainKeys;
+}
+
+// The text after `"key": ` in `line`, or nullptr.
+const char *find_value(const std::string &line, const char *key)
+{
+    const std::string pat = std::string("\"") + key + "\": ";
+    const size_t at = line.find(pat);
+    return at == std::string::npos ? nullptr : line.c_str() + at + pat.size();
+}
+
+bool get_string(const std::string &line, const char *key, std::string *out)
+{
+    const char *p = find_value(line, key);
+    if (!p || *p != '"')
+        return false;
+    const char *q = std::strchr(p + 1, '"');
+    if (!q)
+        return false;
+    out->assign(p + 1, q);
+    return true;
+}
+
+bool get_number(const std::string &line, const char *key, double *out)
+{
+    const char *p = find_value(line, key);
+    if (!p)
+        return false;
+    char *end = nullptr;
+    errno = 0;
+    const double v = std::strtod(p, &end);
+    if (end == p || errno)
+        return false;
+    *out = v;
+    return true;
+}
+
+bool parse_line(const std::string &line, CacheLine *c)
+{
+    if (!get_string(line, "device", &c->device) || !get_string(line, "kind", &c->kind) ||
+        !get_string(line, "tuned_on", &c->tuned_on) || !get_number(line, "ms", &c->ms))
+        return false;
+    if (c->kind != "plain_u64" && c->kind != "plain_u32" && c->kind != "batch")
+        return false;
+    const char *const *keys = keys_of(c->kind);
+    for (int i = 0; i < n_keys(c->kind); ++i) {
+        double v = 0.0;
+        if (!get_number(line, keys[i], &v) || v < 0.0 || v > 4294967295.0 || v != (uint32_t)v)
+            return false;
+        c->v[i] = (uint32_t)v;
+    }
+    return true;
+}
+
+std::string format_line(const CacheLine &c)
+{
+    std::string s = "{\"device\": \"" + c.device + "\", \"kind\": \"" + c.kind + "\"";
+    const char *const *keys = keys_of(c.kind);
+    char buf[96];
+    for (int i = 0; i < n_keys(c.kind); ++i) {
+        std::snprintf(buf, sizeof buf, ", \"%s\": %u", keys[i], c.v[i]);
+        s += buf;
+    }
+    std::snprintf(buf, sizeof buf, ", \"ms\": %.6f", c.ms);
+    s += ", \"tuned_on\": \"" + c.tuned_on + "\"" + buf + "}";
+    return s;
+}
+
+// Read every line of a cache file. A missing file is an empty cache when
+// `missing_ok`.
+int read_cache(const char *path, bool missing_ok, std::vector<CacheLine> *out)
+{
+    out->clear();
+    FILE *f = std::fopen(path, "r");
+    if (!f) {
+        if (missing_ok && errno == ENOENT)
+            return RNGX_OK;
+        return set_error(RNGX_E_INVAL, "tune cache: cannot open %s: %s", path,
+                         std::strerror(errno));
+    }
+    char buf[1024];
+    int lineno = 0;
+    while (std::fgets(buf, sizeof buf, f)) {
+        ++lineno;
+        std::string line(buf);
+        while (!line.empty() && (line.back() == '\n' || line.back() == '\r'))
+            line.pop_back();
+        if (line.empty())
+            continue;
+        CacheLine c;
+        if (!parse_line(line, &c)) {
+            std::fclose(f);
+            return set_error(RNGX_E_INVAL, "tune cache: %s line %d is not a tuning entry", path,
+                             lineno);
+        }
+        out->push_back(c);
+    }
+    std::fclose(f);
+    return RNGX_OK;
+}
+
+// Replace this device's entry of `entry.kind` in the file at `path` (other
+// entries are kept), writing a new file and renaming it over the old one.
+int merge_into_cache(const char *path, const CacheLine &entry)
+{
+    std::vector<CacheLine> lines;
+    int rc = read_cache(path, true, &lines);
+    if (rc)
+        return rc;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f)
+        return set_error(RNGX_E_INVAL, "tune cache: cannot write %s: %s", tmp.c_str(),
+                         std::strerror(errno));
+    bool ok = true;
+    for (const CacheLine &c : lines)
+        if (!(c.device == entry.device && c.kind == entry.kind))
+            ok = ok && std::fprintf(f, "%s\n", format_line(c).c_str()) > 0;
+    ok = ok && std::fprintf(f, "%s\n", format_line(entry).c_str()) > 0;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return set_error(RNGX_E_INVAL, "tune cache: cannot write %s", path);
+    }
+    return RNGX_OK;
+}
+
+const char *env_cache_path()
+{
+    const char *p = std::getenv("RNGX_TUNE_CACHE");
+    return p && *p ? p : nullptr;
+}
+
+} // namespace
+
+int tune_cache_record_batch(const rngx_batch_cfg &cfg, double ms, uint32_t m, uint64_t values)
+{
+    const char *path = env_cache_path();
+    if (!path)
+        return RNGX_OK;
+    CacheLine c;
+    int rc = device_signature(&c.device);
+    if (rc)
+        return rc;
+    c.kind = "batch";
+    const uint32_t v[7] = {cfg.values_per_lane, cfg.waves_per_block, cfg.blocks, cfg.use_graph,
+                           cfg.row_values,      cfg.run_items,       cfg.per_item};
+    std::memcpy(c.v, v, sizeof v);
+    c.ms = ms;
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "m=%u values=%llu", m, (unsigned long long)values);
+    c.tuned_on = buf;
+    return merge_into_cache(path, c);
+}
+
+int tune_cache_apply_env()
+{
+    const char *path = env_cache_path();
+    if (!path)
+        return RNGX_OK;
+    if (FILE *f = std::fopen(path, "r"))
+        std::fclose(f);
+    else if (errno == ENOENT)
+        return RNGX_OK; // nothing tuned yet
+    uint32_t applied = 0;
+    return rngx_tune_cache_load(path, &applied);
+}
+
+} // namespace rngx
+
+using namespace rngx;
+
+extern "C" int rngx_tune_cache_load(const char *path, uint32_t *applied)
+{
+    clear_error();
+    if (!path)
+        return set_error(RNGX_E_INVAL, "rngx_tune_cache_load: path is NULL");
+    std::vector<CacheLine> lines;
+    int rc = read_cache(path, false, &lines);
+    if (rc)
+        return rc;
+    std::string sig;
+    rc = device_signature(&sig);
+    if (rc)
+        return rc;
+    uint32_t n = 0;
+    for (const CacheLine &c : lines) {
+        if (c.device != sig)
+            continue;
+        if (c.kind == "batch") {
+            const rngx_batch_cfg b{c.v[0], c.v[1], c.v[2], c.v[3], c.v[4], c.v[5], c.v[6]};
+            rc = rngx_set_batch_cfg(&b);
+        } else {
+            const rngx_launch l{c.v[0], c.v[1], c.v[2]};
+            rc = rngx_set_launch(c.kind == "plain_u32", &l);
+        }
+        if (rc)
+            return set_error(RNGX_E_INVAL, "tune cache: %s holds an invalid %s entry for %s",
+                             path, c.kind.c_str(), sig.c_str());
+        ++n;
+    }
+    if (applied)
+        *applied = n;
+    return RNGX_OK;
+}
+
+extern "C" int rngx_tune_cache_save(const char *path)
+{
+    clear_error();
+    if (!path)
+        return set_error(RNGX_E_INVAL, "rngx_tune_cache_save: path is NULL");
+    CacheLine c;
+    int rc = device_signature(&c.device);
+    if (rc)
+        return rc;
+    c.tuned_on = "saved";
+    for (int u32 = 0; u32 < 2; ++u32) {
+        rngx_launch l;
+        rc = rngx_get_launch(u32, &l);
+        if (rc)
+            return rc;
+        c.kind = u32 ? "plain_u32" : "plain_u64";
+        const uint32_t v[3] = {l.block, l.chunks, l.nontemporal};
+        std::memset(c.v, 0, sizeof c.v);
+        std::memcpy(c.v, v, sizeof v);
+        rc = merge_into_cache(path, c);
+        if (rc)
+            return rc;
+    }
+    rngx_batch_cfg b;
+    rc = rngx_get_batch_cfg(&b);
+    if (rc)
+        return rc;
+    c.kind = "batch";
+    const uint32_t v[7] = {b.values_per_lane, b.waves_per_block, b.blocks, b.use_graph,
+                           b.row_values,      b.run_items,       b.per_item};
+    std::memcpy(c.v, v, sizeof v);
+    return merge_into_cache(path, c);
+}
+
+extern "C" int rngx_autotune_plain(uint32_t n_iters, int u32, void *out, uint32_t reps,
+                                   void *stream, rngx_plain_tune_result *result)
+{
+    Generator &g = generator();
+    std::lock_guard<std::recursive_mutex> lk(g.mu);
+    clear_error();
+    if (!result)
+        return set_error(RNGX_E_INVAL, "rngx_autotune_plain: result is NULL");
+    if (reps == 0 || n_iters == 0)
+        return set_error(RNGX_E_INVAL, "rngx_autotune_plain: reps and n_iters must be >= 1");
+    if (!g.inited)
+        return set_error(RNGX_E_NOINIT, "rngx_autotune_plain called before rngx_init");
+    const size_t esize = u32 ? 4 : 8;
+    if (!out || reinterpret_cast<uintptr_t>(out) % esize)
+        return set_error(RNGX_E_INVAL, "rngx_autotune_plain: out is NULL or not %zu-byte aligned",
+                         esize);
+    const unsigned __int128 bytes128 = (unsigned __int128)n_iters * g.n * esize;
+    if (bytes128 > (unsigned __int128)SIZE_MAX / 2)
+        return set_error(RNGX_E_INVAL, "rngx_autotune_plain: output size overflows size_t");
+    int rc = check_device_locked(g);
+    if (rc)
+        return rc;
+    const size_t out_bytes = (size_t)bytes128;
+    const size_t state_bytes = (size_t)g.n * 8;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool star = current_scrambler() == RNGX_SCRAMBLE_STAR;
+    std::memset(result, 0, sizeof *result);
+
+    // Snapshot of the states: every candidate starts from it, so all of them
+    // write the same values, and the generator is left as it was.
+    struct Scratch {
+        void *snap = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Scratch()
+        {
+            if (snap)
+                RNGX_NOTE(hipFree(snap));
+            if (e0)
+                RNGX_NOTE(hipEventDestroy(e0));
+            if (e1)
+                RNGX_NOTE(hipEventDestroy(e1));
+        }
+    } sc;
+    hipError_t e = hipMalloc(&sc.snap, state_bytes);
+    if (e != hipSuccess) {
+        sc.snap = nullptr;
+        (void)hipGetLastError(); // this allocation's own error, reported below
+        return set_error(RNGX_E_NOMEM, "rngx_autotune_plain: cannot allocate %zu bytes of "
+                                       "snapshot: %s",
+                         state_bytes, hipGetErrorString(e));
+    }
+    RNGX_HIP(hipEventCreate(&sc.e0));
+    RNGX_HIP(hipEventCreate(&sc.e1));
+    RNGX_HIP(hipStreamWaitEvent(s, g.state_ready, 0));
+    RNGX_HIP(hipMemcpyAsync(sc.snap, g.state, state_bytes, hipMemcpyDeviceToDevice, s));
+
+    // The output checked as 64-bit words (a u32 output of odd length leaves
+    // its last value out of the checksum).
+    const uint64_t words = out_bytes / 8;
+    uint64_t ref_sum = 0;
+    bool have_ref = false;
+    double best = 1e300;
+    const uint32_t blocks[3] = {256, 512, 1024};
+    const uint32_t chunks[3] = {1, 2, 4};
+    auto restore = [&]() -> int {
+        RNGX_HIP(hipMemcpyAsync(g.state, sc.snap, state_bytes, hipMemcpyDeviceToDevice, s));
+        return RNGX_OK;
+    };
+    for (uint32_t bi = 0; bi < 3; ++bi) {
+        for (uint32_t ci = 0; ci < 3; ++ci) {
+            for (uint32_t nt = 0; nt < 2; ++nt) {
+                const rngx_launch cfg{blocks[bi], chunks[ci], nt};
+                // Warm-up, then the output check.
+                if ((rc = restore()))
+                    return rc;
+                take_stray_error("before an autotuned rng kernel launch");
+                RNGX_HIP(launch_gen(cfg, u32 != 0, star, g.state, g.n, n_iters, out, s));
+                uint64_t sum = 0;
+                rc = rngx_checksum(static_cast<const uint64_t *>(out), words, s, &sum);
+                if (rc)
+                    return rc;
+                if (!have_ref) {
+                    ref_sum = sum;
+                    have_ref = true;
+                } else if (sum != ref_sum) {
+                    return set_error(RNGX_E_HIP,
+                                     "autotune: configuration (block=%u, chunks=%u, nt=%u) "
+                                     "produced a different output",
+                                     cfg.block, cfg.chunks, cfg.nontemporal);
+                }
+                double total_ms = 0.0;
+                for (uint32_t r = 0; r < reps; ++r) {
+                    if ((rc = restore()))
+                        return rc;
+                    RNGX_HIP(hipEventRecord(sc.e0, s));
+                    RNGX_HIP(launch_gen(cfg, u32 != 0, star, g.state, g.n, n_iters, out, s));
+                    RNGX_HIP(hipEventRecord(sc.e1, s));
+                    RNGX_HIP(hipEventSynchronize(sc.e1));
+                    float ms = 0.f;
+                    RNGX_HIP(hipEventElapsedTime(&ms, sc.e0, sc.e1));
+                    total_ms += ms;
+                }
+                const double mean = total_ms / reps;
+                if (result->n_tried < RNGX_TUNE_MAX) {
+                    result->tried[result->n_tried].cfg = cfg;
+                    result->tried[result->n_tried].ms = mean;
+                }
+                ++result->n_tried;
+                if (mean < best) {
+                    best = mean;
+                    result->best = cfg;
+                }
+            }
+        }
+    }
+    // Leave the generator exactly as it was (state and cursor).
+    if ((rc = restore()))
+        return rc;
+    RNGX_HIP(hipEventRecord(g.state_ready, s));
+    RNGX_HIP(hipStreamSynchronize(s));
+    result->best_ms = best;
+    result->best_gbs = ((double)out_bytes + 16.0 * g.n) / (best * 1e-3) / 1e9;
+    (u32 ? g.cfg32 : g.cfg64) = result->best;
+    if (const char *path = env_cache_path()) {
+        CacheLine c;
+        rc = device_signature(&c.device);
+        if (rc)
+            return rc;
+        c.kind = u32 ? "plain_u32" : "plain_u64";
+        c.v[0] = result->best.block;
+        c.v[1] = result->best.chunks;
+        c.v[2] = result->best.nontemporal;
+        c.ms = best;
+        char buf[96];
+        std::snprintf(buf, sizeof buf, "n=%u iters=%u", g.n, n_iters);
+        c.tuned_on = buf;
+        return merge_into_cache(path, c);
+    }
+    return RNGX_OK;
+}

@@ -58,6 +58,21 @@ class TuneResult(ctypes.Structure):
                 ("tried", TuneEntry * 128)]
 
 
+class Launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
+                ("nontemporal", ctypes.c_uint32)]
+
+
+class PlainTuneEntry(ctypes.Structure):
+    _fields_ = [("cfg", Launch), ("ms", ctypes.c_double)]
+
+
+class PlainTuneResult(ctypes.Structure):
+    _fields_ = [("best", Launch), ("best_ms", ctypes.c_double), ("best_gbs", ctypes.c_double),
+                ("n_tried", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("tried", PlainTuneEntry * 128)]
+
+
 class ServeReport(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "released", "pending",
                                                 "admitted", "inflight_batches", "batches",
@@ -71,11 +86,6 @@ class ServeReport(ctypes.Structure):
                 ("pool_used_bytes", ctypes.c_uint64), ("pool_peak_bytes", ctypes.c_uint64),
                 ("lag_p50_us", ctypes.c_double), ("lag_p99_us", ctypes.c_double),
                 ("lag_max_us", ctypes.c_double)]
-
-
-class Launch(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
-                ("nontemporal", ctypes.c_uint32)]
 
 
 class ProfEvent(ctypes.Structure):
@@ -124,12 +134,16 @@ _SIGS = {
     "rngx_stream_to_host": ([_u32, _u32, _int, _p, _p, ctypes.c_size_t, _p, _u32, CONSUME_FN,
                              _p, _p, _p], _int),
     "rngx_set_copy_mode": ([_int, _u32], _int),
+    "rngx_inject_copy_failure": ([_u64], _int),
     "rngx_get_copy_mode": ([ctypes.POINTER(_int), ctypes.POINTER(_u32)], _int),
     "rngx_generate_batch": ([_p, _u32, _p, _u64, _p], _int),
     "rngx_set_batch_cfg": ([ctypes.POINTER(BatchCfg)], _int),
     "rngx_get_batch_cfg": ([ctypes.POINTER(BatchCfg)], _int),
     "rngx_autotune_batch": ([_p, _u32, _p, _u64, _u32, _p, ctypes.POINTER(TuneResult)], _int),
     "rngx_checksum": ([_p, _u64, _p, ctypes.POINTER(_u64)], _int),
+    "rngx_autotune_plain": ([_u32, _int, _p, _u32, _p, ctypes.POINTER(PlainTuneResult)], _int),
+    "rngx_tune_cache_save": ([ctypes.c_char_p], _int),
+    "rngx_tune_cache_load": ([ctypes.c_char_p, ctypes.POINTER(_u32)], _int),
     "rngx_initial_state": ([_u64, _u32, ctypes.POINTER(_u64)], _int),
     "rngx_jump_ahead": ([_u64, _u64, ctypes.POINTER(_u64)], _int),
     "rngx_serve_start": ([_u64, _u32, _p, _u64, _u32, _u32], _int),
@@ -325,6 +339,12 @@ def stream_to_host(n_steps: int, iters_per_step: int, dev0, dev1, host, host_slo
     _check(rc)
 
 
+def inject_copy_failure(step: int):
+    """Make the copy of `step` fail in the next stream_to_host call (test
+    hook; 2**64 - 1 disarms it)."""
+    _check(lib().rngx_inject_copy_failure(step))
+
+
 def set_copy_mode(mode: int, blocks: int = 16):
     _check(lib().rngx_set_copy_mode(mode, blocks))
 
@@ -400,6 +420,34 @@ def autotune_batch(reqs, out, reps=2, stream=None):
     n = min(res.n_tried, 128)
     return {"best": _cfg_dict(res.best), "best_ms": res.best_ms, "best_gbs": res.best_gbs,
             "tried": [(_cfg_dict(res.tried[i].cfg), res.tried[i].ms) for i in range(n)]}
+
+
+def _launch_dict(c):
+    return {"block": c.block, "chunks": c.chunks, "nontemporal": bool(c.nontemporal)}
+
+
+def autotune_plain(n_iters, out, reps=2, u32=False, stream=None):
+    """Time every plain launch configuration at the current generator's shape
+    for n_iters iterations; keep the fastest (state and cursor unchanged;
+    `out` receives the next n_iters iterations)."""
+    n = info()[1]
+    optr = _device_buffer(out, 4 if u32 else 8, n_iters * n)
+    res = PlainTuneResult()
+    _check(lib().rngx_autotune_plain(n_iters, int(bool(u32)), optr, reps, stream_handle(stream),
+                                     ctypes.byref(res)))
+    k = min(res.n_tried, 128)
+    return {"best": _launch_dict(res.best), "best_ms": res.best_ms, "best_gbs": res.best_gbs,
+            "tried": [(_launch_dict(res.tried[i].cfg), res.tried[i].ms) for i in range(k)]}
+
+
+def tune_cache_save(path):
+    _check(lib().rngx_tune_cache_save(os.fsencode(path)))
+
+
+def tune_cache_load(path) -> int:
+    n = _u32()
+    _check(lib().rngx_tune_cache_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
 
 
 def checksum(t, n=None, stream=None) -> int:

@@ -227,6 +227,31 @@ def test_batch_argument_errors_without_gpu():
     rngx.set_batch_cfg()
 
 
+def test_tune_cache_errors_without_gpu(tmp_path):
+    L = rngx.lib()
+    assert L.rngx_tune_cache_load(None, None) == rngx.RNGX_E_INVAL
+    assert L.rngx_tune_cache_save(None) == rngx.RNGX_E_INVAL
+    assert L.rngx_tune_cache_load(str(tmp_path / "missing.jsonl").encode(), None) == rngx.RNGX_E_INVAL
+    assert "cannot open" in rngx.last_error()
+    # Lines are checked before the device is asked for: a truncated entry,
+    # an unknown kind and a non-integer field are each rejected by line.
+    good = ('{"device": "gfx950 256cu", "kind": "plain_u64", "block": 512, "chunks": 4, '
+            '"nontemporal": 0, "ms": 1.000000, "tuned_on": "n=1 iters=1"}')
+    for bad in ['{"device": "x", "kind": "plain_u64", "block": 512}',
+                good.replace("plain_u64", "plain_u16"),
+                good.replace('"chunks": 4', '"chunks": 4.5'),
+                good.replace('"block": 512', '"block": -1')]:
+        f = tmp_path / "c.jsonl"
+        f.write_text(good + "\n" + bad + "\n")
+        assert L.rngx_tune_cache_load(str(f).encode(), None) == rngx.RNGX_E_INVAL, bad
+        assert "line 2" in rngx.last_error()
+    # The plain autotuner needs an initialised generator.
+    res = rngx.PlainTuneResult()
+    assert L.rngx_autotune_plain(4, 0, 16, 1, None, ctypes.byref(res)) == rngx.RNGX_E_NOINIT
+    assert L.rngx_autotune_plain(4, 0, 16, 0, None, ctypes.byref(res)) == rngx.RNGX_E_INVAL
+    assert L.rngx_autotune_plain(4, 0, 16, 1, None, None) == rngx.RNGX_E_INVAL
+
+
 def test_serve_calls_before_start_are_noinit():
     L = rngx.lib()
     t = rngx._u64()

@@ -167,7 +167,7 @@ def test_autotune_agrees_across_candidates(oracle):
     res = rngx.autotune_batch(_reqs(r), out, reps=1)
     assert len(res["tried"]) >= 32 and res["best_ms"] > 0
     assert {c["run_items"] for c, _ in res["tried"]} == {1, 8}
-    assert {c["per_item"] for c, _ in res["tried"]} == {False, True}
+    assert {c["per_item"] for c, _ in res["tried"]} == {False}
     assert rngx.get_batch_cfg() == res["best"]
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint64),

@@ -324,3 +324,66 @@ def test_cursor_may_not_pass_the_last_value_number(oracle):
     rngx.generate(3, out)
     assert rngx.info()[2] == 2**64 - 1
     assert rngx.lib().rngx_generate(1, out.data_ptr(), None) == rngx.RNGX_E_INVAL
+
+
+@pytest.mark.parametrize("u32", [False, True])
+def test_plain_autotuner_keeps_state_and_output(oracle, u32):
+    # Every candidate starts from the same snapshot: the tuner's output is
+    # the next n_iters iterations, the cursor does not move, and the fastest
+    # configuration becomes the launch configuration of that output type.
+    seed, n, iters = 9, 12345, 6
+    old = rngx.get_launch(u32)
+    try:
+        rngx.init(seed, n)
+        pre = torch.empty(3 * n, dtype=torch.int64, device="cuda")
+        rngx.generate(3, pre)
+        out = torch.zeros(iters * n + 1, dtype=torch.int32 if u32 else torch.int64, device="cuda")
+        res = rngx.autotune_plain(iters, out, reps=1, u32=u32)
+        assert len(res["tried"]) == 18 and res["best_ms"] > 0
+        assert rngx.get_launch(u32) == res["best"]
+        assert rngx.info()[2] == 3
+        exp = oracle.generate(seed, n, 3 + 2 * iters)
+        got = (_u32 if u32 else _u64)(out)
+        assert got[-1] == 0
+        want = exp[3:3 + iters]
+        if u32:
+            want = (want & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+        assert np.array_equal(got[:-1].reshape(iters, n), want)
+        # The generator continues from where it was before tuning.
+        nxt = torch.empty(iters * n, dtype=torch.int64, device="cuda")
+        rngx.generate(iters, nxt)
+        torch.cuda.synchronize()
+        assert np.array_equal(_u64(nxt).reshape(iters, n), exp[3:3 + iters])
+    finally:
+        rngx.set_launch(u32, **old)
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    rngx.init(1, 4096)
+    old64, old32, oldb = rngx.get_launch(False), rngx.get_launch(True), rngx.get_batch_cfg()
+    path = tmp_path / "tune.jsonl"
+    try:
+        rngx.set_launch(False, 1024, 2, True)
+        rngx.set_launch(True, 256, 1, False)
+        rngx.set_batch_cfg(128, 2, 77, False, 16, 8, False)
+        rngx.tune_cache_save(path)
+        # An entry of another device is kept on save and ignored on load.
+        other = ('{"device": "gfx000 1cu", "kind": "plain_u64", "block": 64, "chunks": 1, '
+                 '"nontemporal": 0, "tuned_on": "x", "ms": 0.000000}')
+        path.write_text(other + "\n" + path.read_text())
+        rngx.set_launch(False, 512, 4, False)
+        rngx.set_launch(True, 512, 4, False)
+        rngx.set_batch_cfg()
+        assert rngx.tune_cache_load(path) == 3
+        assert rngx.get_launch(False) == {"block": 1024, "chunks": 2, "nontemporal": True}
+        assert rngx.get_launch(True) == {"block": 256, "chunks": 1, "nontemporal": False}
+        assert rngx.get_batch_cfg() == {"values_per_lane": 128, "waves_per_block": 2,
+                                        "blocks": 77, "use_graph": False, "row_values": 16,
+                                        "run_items": 8, "per_item": False}
+        rngx.tune_cache_save(path)
+        lines = path.read_text().splitlines()
+        assert lines[0] == other and len(lines) == 4
+    finally:
+        rngx.set_launch(False, **old64)
+        rngx.set_launch(True, **old32)
+        rngx.set_batch_cfg(**oldb)

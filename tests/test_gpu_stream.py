@@ -111,6 +111,42 @@ def test_consumer_exception_stops_and_propagates(oracle):
     assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle.generate(seed, n, 1, cursor=c)[0])
 
 
+def test_forced_copy_failure_stops_and_reports(oracle, copy_mode):
+    # The copy of step 5 fails (forced on the host, before it is enqueued):
+    # the call drains both streams, hands no further step to the consumer,
+    # and reports the failure; the library stays usable and the cursor has
+    # advanced past every generated step.
+    seed, n, ips = 6, 4096, 2
+    try:
+        rngx.init(seed, n)
+        dev0, dev1, host = _buffers(n, ips, 2)
+        exp = oracle.generate(seed, n, 40 * ips)
+        seen = []
+
+        def consume(step, arr):
+            seen.append(step)
+            assert np.array_equal(arr.reshape(ips, n), exp[step * ips:(step + 1) * ips])
+        rngx.inject_copy_failure(5)
+        with pytest.raises(rngx.RngxError) as ei:
+            rngx.stream_to_host(20, ips, dev0, dev1, host, 2, consume=consume)
+        assert ei.value.code == rngx.RNGX_E_HIP
+        assert "step 5" in str(ei.value) and "forced" in str(ei.value)
+        assert seen == [0, 1, 2, 3]
+        assert rngx.info()[2] == 6 * ips
+        # The hook fired once: the next run streams in full from the cursor.
+        seen.clear()
+        rngx.stream_to_host(4, ips, dev0, dev1, host, 2, consume=lambda k, a: seen.append(
+            (k, np.array_equal(a.reshape(ips, n), exp[(6 + k) * ips:(7 + k) * ips]))))
+        assert seen == [(k, True) for k in range(4)]
+        # Armed for a step beyond the run: it does not fire, and it is
+        # disarmed when the run ends.
+        rngx.inject_copy_failure(100)
+        rngx.stream_to_host(2, ips, dev0, dev1, host, 2)
+        assert rngx.info()[2] == 12 * ips
+    finally:
+        rngx.inject_copy_failure(2**64 - 1)
+
+
 def test_pageable_host_memory_uses_runtime_copy(oracle):
     # Ordinary (not page-locked) host memory cannot be written by the copy
     # kernel; the pipeline must still deliver every value.
