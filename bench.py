@@ -254,7 +254,8 @@ def serving(torch, rngx, seconds, plain_gbs):
     res = {"workload": "2^20 resident streams, 16 GB pool, lengths floor(2^U[12,22)), "
                        "Poisson arrivals, %.0f s per rate" % seconds, "rates": []}
     try:
-        for rate in (2000.0, 10000.0, 50000.0):
+        # seconds = 0: the saturation run alone (for profiling it).
+        for rate in (2000.0, 10000.0, 50000.0) if seconds > 0 else ():
             t, g, L = inputs.serving_arrivals(rate, seconds)
             st = rngx.serve_run_trace(t, g, L, timeout_s=seconds + 120)
             row = {"rate_req_s": rate, "requests": st["completed"],
@@ -413,6 +414,53 @@ def cpu_baseline(n_total, iters, min_seconds=10.0, single_seconds=5.0):
     return res
 
 
+def trace_summary(path, match, split_ms):
+    """Device occupancy of the kernels whose names contain `match`, from a
+    rocprofv3 kernel trace (the SQLite results database): the dispatches are
+    cut into runs wherever the device stays idle longer than `split_ms`; per
+    run, the span from the first start to the last end, the busy time (union
+    of the kernels' intervals), the idle gaps between busy periods, and the
+    mean number of kernels in flight."""
+    import sqlite3
+    db = sqlite3.connect(path)
+    cols = [r[1] for r in db.execute("pragma table_info(kernels)")]
+    end = "end" if "end" in cols else "start + duration"
+    rows = db.execute('select name, start, %s, queue_id from kernels order by start' % end).fetchall()
+    ks = [(int(a), int(b), q) for nm, a, b, q in rows if match in nm]
+    runs, cur, reach = [], [], 0
+    for a, b, q in ks:
+        if cur and a - reach > split_ms * 1e6:
+            runs.append(cur)
+            cur = []
+        reach = max(reach, b) if cur else b
+        cur.append((a, b, q))
+    if cur:
+        runs.append(cur)
+    out = []
+    for r in runs:
+        span = max(b for _, b, _ in r) - r[0][0]
+        busy, gaps, s0, e0 = 0, [], r[0][0], r[0][1]
+        for a, b, _ in r[1:]:
+            if a > e0:
+                busy += e0 - s0
+                gaps.append(a - e0)
+                s0, e0 = a, b
+            else:
+                e0 = max(e0, b)
+        busy += e0 - s0
+        gaps.sort()
+        pct = lambda p: gaps[min(len(gaps) - 1, int(p * len(gaps)))] / 1e3 if gaps else 0.0
+        out.append({"kernels": len(r), "queues": sorted({q for _, _, q in r}),
+                    "span_ms": round(span / 1e6, 3), "busy_ms": round(busy / 1e6, 3),
+                    "busy_frac": round(busy / span, 4) if span else 1.0,
+                    "gaps": len(gaps), "gap_total_ms": round(sum(gaps) / 1e6, 3),
+                    "gap_p50_us": round(pct(0.5), 2), "gap_p99_us": round(pct(0.99), 2),
+                    "gap_max_us": round(gaps[-1] / 1e3, 2) if gaps else 0.0,
+                    "kernel_sum_ms": round(sum(b - a for a, b, _ in r) / 1e6, 3),
+                    "mean_in_flight": round(sum(b - a for a, b, _ in r) / busy, 3) if busy else 0})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,7 +469,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the size/dtype sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
-                    help="duration of each Poisson serving run")
+                    help="duration of each Poisson serving run (0: only the saturation run)")
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline kernel (for profiling)")
     ap.add_argument("--batched-only", action="store_true",
@@ -437,7 +485,18 @@ def main():
                     help="only run a plain 16 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--placement-probe", action="store_true",
                     help="only time one launch shape into three separately allocated buffers")
+    ap.add_argument("--trace-summary", metavar="RESULTS_DB",
+                    help="only summarise device occupancy in a rocprofv3 kernel trace")
+    ap.add_argument("--trace-kernels", default="batch",
+                    help="with --trace-summary: kernels whose names contain this text")
+    ap.add_argument("--trace-split-ms", type=float, default=5.0,
+                    help="with --trace-summary: idle time that separates two runs")
     args = ap.parse_args()
+    if args.trace_summary:
+        for i, run in enumerate(trace_summary(args.trace_summary, args.trace_kernels,
+                                              args.trace_split_ms)):
+            print(json.dumps(dict(run=i, **run)), flush=True)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         log("bench.py measures a single GPU: the generator shards across GPUs with no "
