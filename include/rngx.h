@@ -285,6 +285,30 @@ typedef struct rngx_req {
 int rngx_generate_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_t out_cap,
                         void *stream);
 
+/* For callers that cannot allocate (code that must not call hipMalloc:
+ * under HIP graph capture, tight serving loops, harnesses that forbid it):
+ * the same output as rngx_generate_batch, from a call that allocates
+ * nothing. The request table goes to a static device array of the library
+ * (262,272 bytes, one per device, held until the process ends) instead of
+ * a buffer allocated for the batch; the jump tables are static device arrays
+ * too. The launch is direct (never a captured graph) in the batch
+ * configuration's launch shape; no profiler events are recorded.
+ * reqs, m, out, out_cap, stream: as rngx_generate_batch; at most
+ * RNGX_NOALLOC_MAX_REQS requests. The table is copied from pageable host
+ * memory, which HIP does synchronously, so the call may block until the
+ * work already queued on `stream` has run; the kernel itself runs
+ * asynchronously.
+ * Every call on a device shares that device's table: calls that overlap on
+ * one device (other threads, or other streams whose kernels are still
+ * running) race. The first call on a device (or any earlier batched call
+ * there) fills its jump tables and takes the table's device address:
+ * set-up, once per device.
+ * Errors: as rngx_generate_batch; RNGX_E_INVAL for m above
+ * RNGX_NOALLOC_MAX_REQS, checked before any device work. */
+#define RNGX_NOALLOC_MAX_REQS 4096u
+int rngx_generate_batch_noalloc(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_t out_cap,
+                                void *stream);
+
 /* Launch configuration of the batched kernel.
  * values_per_lane: S, values each lane produces per work item (16, 32, 64,
  *   128, 256, 512 or 1024); a work item is a tile of 64 * S output values.

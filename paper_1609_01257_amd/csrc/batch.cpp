@@ -63,7 +63,23 @@ struct BatchGlobals {
     DevTables dev[kMaxDevices];
     rngx_batch_cfg cfg{256, 4, 0, 1, 16, 1, 0};
     BatchSlot api_slot;
+    // Device address of `scratch` per device (rngx_generate_batch_noalloc),
+    // taken once on the device's first such call.
+    unsigned char *scratch_ptr[kMaxDevices] = {};
 };
+
+// Request table of rngx_generate_batch_noalloc: a BatchDesc, then up to
+// RNGX_NOALLOC_MAX_REQS records at kReqOffset (262,272 bytes). One copy per
+// device, held until the process ends; every such call on a device rewrites
+// it, so calls that overlap on one device race. In host code the name is a
+// stand-in for the symbol, never a device address: the address comes from
+// hipGetSymbolAddress (scratch_ptr above).
+constexpr size_t kScratchBytes = kReqOffset + (size_t)RNGX_NOALLOC_MAX_REQS * sizeof(BatchReq);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+// Its host image, built under the batch lock and copied with one
+// hipMemcpyAsync. The copy is from pageable memory, which HIP performs
+// synchronously, so the image may be rewritten as soon as the copy returns.
+alignas(256) unsigned char g_noalloc_host[kScratchBytes];
 
 BatchGlobals &G()
 {
@@ -82,17 +98,22 @@ void free_acc(DevTables &t)
     t.h_acc = nullptr;
 }
 
-// Host images of the lane-spread and carry tables for every allowed S.
-void build_host_tables(std::vector<uint64_t> &spread, std::vector<uint64_t> &nib)
+// Host images of the lane-spread and carry tables for every allowed S, in
+// static host memory (built under tables_mu, once per device): filling the
+// device tables allocates nothing.
+uint64_t g_spread_host[kNumS * kSpreadTable];
+uint64_t g_carry_host[kNumS * kCarryTable];
+
+void build_host_tables(uint64_t *spread, uint64_t *nib)
 {
-    spread.assign((size_t)kNumS * kSpreadTable, 0);
-    nib.assign((size_t)kNumS * kCarryTable, 0);
+    std::memset(spread, 0, sizeof(uint64_t) * kNumS * kSpreadTable);
+    std::memset(nib, 0, sizeof(uint64_t) * kNumS * kCarryTable);
     for (int i = 0; i < kNumS; ++i) {
         const uint64_t S = kValuesPerLane[i];
         // Lane spread: entry ((16 q + v) * 64 + m) is T^(m S) (v << 4q),
         // so a lane m places above a wave-uniform state z with the XOR of
         // one entry per nibble of z.
-        uint64_t *sp = spread.data() + (size_t)kSpreadTable * i;
+        uint64_t *sp = spread + (size_t)kSpreadTable * i;
         for (uint32_t m = 0; m < 64; ++m) {
             uint64_t rows[64], col[64] = {0};
             power_rows(m * S, rows);
@@ -118,7 +139,7 @@ void build_host_tables(std::vector<uint64_t> &spread, std::vector<uint64_t> &nib
         for (int r = 0; r < 64; ++r)
             for (int j = 0; j < 64; ++j)
                 col[j] |= ((carry_rows[r] >> j) & 1u) << r;
-        uint64_t *t = nib.data() + (size_t)kCarryTable * i;
+        uint64_t *t = nib + (size_t)kCarryTable * i;
         for (int q = 0; q < 16; ++q)
             for (int v = 0; v < 16; ++v)
                 for (int b = 0; b < 4; ++b)
@@ -167,8 +188,7 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **spread_all, int 
     if (!t.loaded) {
         // Device addresses of this device's copies of the static tables
         // (the arrays' names are host-side stand-ins), then their contents.
-        std::vector<uint64_t> spread, nib;
-        build_host_tables(spread, nib);
+        build_host_tables(g_spread_host, g_carry_host);
         void *p2 = nullptr, *ps = nullptr, *pc = nullptr;
         int cus = 0;
         hipError_t e = hipGetSymbolAddress(&p2, HIP_SYMBOL(g_pow2));
@@ -179,9 +199,9 @@ int batch_tables_locked(const uint64_t **pow2, const uint64_t **spread_all, int 
         if (e == hipSuccess)
             e = hipMemcpy(p2, jump_tables(), sizeof g_pow2, hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMemcpy(ps, spread.data(), sizeof g_spread, hipMemcpyHostToDevice);
+            e = hipMemcpy(ps, g_spread_host, sizeof g_spread, hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMemcpy(pc, nib.data(), sizeof g_carry_nib, hipMemcpyHostToDevice);
+            e = hipMemcpy(pc, g_carry_host, sizeof g_carry_nib, hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess)
@@ -448,6 +468,21 @@ void release_batch()
         RNGX_NOTE(hipSetDevice(cur));
 }
 
+// Device address of this device's `scratch` (once per device, under the
+// batch lock).
+int noalloc_scratch_locked(BatchGlobals &g, int dev, unsigned char **ptr)
+{
+    if (!g.scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress (batch scratch)");
+        g.scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *ptr = g.scratch_ptr[dev];
+    return RNGX_OK;
+}
+
 rngx_batch_cfg current_batch_cfg()
 {
     BatchGlobals &g = G();
@@ -506,6 +541,94 @@ extern "C" int rngx_generate_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
         return RNGX_OK;
     return batch_launch(g.api_slot, g.cfg, current_scrambler() == RNGX_SCRAMBLE_STAR,
                         static_cast<hipStream_t>(stream));
+}
+
+extern "C" int rngx_generate_batch_noalloc(const rngx_req *reqs, uint32_t m, uint64_t *out,
+                                           uint64_t out_cap, void *stream)
+{
+    BatchGlobals &g = G();
+    std::lock_guard<std::mutex> lk(g.mu);
+    clear_error();
+    if (m > RNGX_NOALLOC_MAX_REQS)
+        return set_error(RNGX_E_INVAL,
+                         "rngx_generate_batch_noalloc: %u requests exceed the limit of %u", m,
+                         (unsigned)RNGX_NOALLOC_MAX_REQS);
+    uint64_t total = 0;
+    int rc = batch_validate(reqs, m, out, out_cap, &total);
+    if (rc || total == 0)
+        return rc;
+    int dev = -1;
+    RNGX_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(RNGX_E_INVAL, "batch: device %d is beyond the %d the library supports",
+                         dev, kMaxDevices);
+    unsigned char *dscratch = nullptr;
+    rc = noalloc_scratch_locked(g, dev, &dscratch);
+    if (rc)
+        return rc;
+    // The jump tables are static device arrays too; the device's first
+    // batched call of any kind fills them.
+    const uint64_t *pow2 = nullptr, *spread_all = nullptr, *nib_all = nullptr;
+    int n_cus = 0;
+    rc = batch_tables_locked(&pow2, &spread_all, &n_cus, &nib_all);
+    if (rc)
+        return rc;
+    rngx_batch_cfg cfg = resolved_cfg(g.cfg, n_cus);
+    const uint64_t C = 64ull * cfg.values_per_lane;
+
+    // The table, staged as the allocating call stages it (packed layout:
+    // a value's virtual index is its output index; empty requests dropped).
+    BatchDesc *desc = reinterpret_cast<BatchDesc *>(g_noalloc_host);
+    BatchReq *tab = reinterpret_cast<BatchReq *>(g_noalloc_host + kReqOffset);
+    uint32_t k = 0;
+    uint64_t base = 0, n_items = 0;
+    for (uint32_t j = 0; j < m; ++j) {
+        const uint64_t len = reqs[j].length;
+        if (len) {
+            n_items += make_record(tab[k], reqs[j].offset, len, base, n_items, reqs[j].gid,
+                                   seed_mix(reqs[j].seed), out + base, C);
+            ++k;
+        }
+        base += len;
+    }
+    std::memset(desc, 0, sizeof *desc); // next_item = 0: the upload resets the work counter
+    desc->reqs = reinterpret_cast<const BatchReq *>(dscratch + kReqOffset);
+    desc->states = nullptr;
+    desc->n_items = n_items;
+    desc->m = k;
+
+    const uint64_t need = (n_items + cfg.waves_per_block - 1) / cfg.waves_per_block;
+    if (cfg.per_item) {
+        if (need > 0x7fffffffull)
+            return set_error(RNGX_E_INVAL, "batch: %llu work items exceed one grid",
+                             (unsigned long long)n_items);
+        cfg.blocks = (uint32_t)std::max<uint64_t>(1, need);
+    } else if (need < cfg.blocks) {
+        cfg.blocks = (uint32_t)std::max<uint64_t>(1, need);
+    }
+    BatchTables tabs;
+    tabs.pow2 = pow2;
+    tabs.spread = spread_all + (size_t)kSpreadTable * batch_s_index(cfg.values_per_lane);
+    tabs.carry_nib = nib_all + kCarryTable * batch_s_index(cfg.values_per_lane);
+    const bool star = current_scrambler() == RNGX_SCRAMBLE_STAR;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (cfg.per_item && k <= kSmallReqs) {
+        SmallTable st;
+        std::memcpy(&st.desc, desc, sizeof(BatchDesc));
+        std::memcpy(st.reqs, tab, (size_t)k * sizeof(BatchReq));
+        take_stray_error("before the allocation-free batch kernel launch");
+        hipError_t e = launch_batch_small(cfg, st, tabs, star, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "batch kernel launch");
+        return RNGX_OK;
+    }
+    RNGX_HIP(hipMemcpyAsync(dscratch, g_noalloc_host, kReqOffset + (size_t)k * sizeof(BatchReq),
+                            hipMemcpyHostToDevice, s));
+    take_stray_error("before the allocation-free batch kernel launch");
+    hipError_t e = launch_batch(cfg, reinterpret_cast<const BatchDesc *>(dscratch), tabs, star, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "batch kernel launch");
+    return RNGX_OK;
 }
 
 extern "C" int rngx_set_batch_cfg(const rngx_batch_cfg *cfg)

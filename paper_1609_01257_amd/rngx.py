@@ -137,6 +137,7 @@ _SIGS = {
     "rngx_inject_copy_failure": ([_u64], _int),
     "rngx_get_copy_mode": ([ctypes.POINTER(_int), ctypes.POINTER(_u32)], _int),
     "rngx_generate_batch": ([_p, _u32, _p, _u64, _p], _int),
+    "rngx_generate_batch_noalloc": ([_p, _u32, _p, _u64, _p], _int),
     "rngx_set_batch_cfg": ([ctypes.POINTER(BatchCfg)], _int),
     "rngx_get_batch_cfg": ([ctypes.POINTER(BatchCfg)], _int),
     "rngx_autotune_batch": ([_p, _u32, _p, _u64, _u32, _p, ctypes.POINTER(TuneResult)], _int),
@@ -387,6 +388,21 @@ def generate_batch(reqs, out, stream=None):
     optr = _device_buffer(out, 8, total) if total else (out.data_ptr() if out is not None else 0)
     cap = out.numel() if out is not None else 0
     _check(lib().rngx_generate_batch(ptr, len(reqs), optr, cap, stream_handle(stream)))
+    return total
+
+
+NOALLOC_MAX_REQS = 4096
+
+
+def generate_batch_noalloc(reqs, out, stream=None):
+    """generate_batch through the entry point that allocates nothing (its
+    request table is a static device array; at most NOALLOC_MAX_REQS
+    requests; calls that overlap on one device race)."""
+    reqs, ptr = _reqs_arg(reqs)
+    total = int(reqs["length"].sum()) if len(reqs) else 0
+    optr = _device_buffer(out, 8, total) if total else (out.data_ptr() if out is not None else 0)
+    cap = out.numel() if out is not None else 0
+    _check(lib().rngx_generate_batch_noalloc(ptr, len(reqs), optr, cap, stream_handle(stream)))
     return total
 
 

@@ -227,6 +227,23 @@ def test_batch_argument_errors_without_gpu():
     rngx.set_batch_cfg()
 
 
+def test_noalloc_batch_argument_errors_without_gpu():
+    L = rngx.lib()
+    big = rngx.make_reqs([1] * (rngx.NOALLOC_MAX_REQS + 1), range(rngx.NOALLOC_MAX_REQS + 1),
+                         [0] * (rngx.NOALLOC_MAX_REQS + 1), [1] * (rngx.NOALLOC_MAX_REQS + 1))
+    # More requests than the static table holds: rejected before any device work.
+    assert L.rngx_generate_batch_noalloc(big.ctypes.data, len(big), 16, len(big),
+                                         None) == rngx.RNGX_E_INVAL
+    assert "exceed the limit of %d" % rngx.NOALLOC_MAX_REQS in rngx.last_error()
+    # The allocating call's argument checks apply unchanged.
+    reqs = rngx.make_reqs([1], [0], [0], [4])
+    assert L.rngx_generate_batch_noalloc(None, 3, None, 0, None) == rngx.RNGX_E_INVAL
+    assert L.rngx_generate_batch_noalloc(reqs.ctypes.data, 1, None, 3, None) == rngx.RNGX_E_INVAL
+    assert L.rngx_generate_batch_noalloc(reqs.ctypes.data, 1, 8, 4, None) == rngx.RNGX_E_INVAL
+    # Nothing requested: a successful no-op that touches no device.
+    assert L.rngx_generate_batch_noalloc(None, 0, None, 0, None) == rngx.RNGX_OK
+
+
 def test_tune_cache_errors_without_gpu(tmp_path):
     L = rngx.lib()
     assert L.rngx_tune_cache_load(None, None) == rngx.RNGX_E_INVAL
