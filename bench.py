@@ -312,7 +312,7 @@ def serving(torch, rngx, seconds, plain_gbs):
             if off + size > words.numel():
                 off = 0
             places.append(words[off:off + size])
-            off += (size + 1) & ~1       # keep every batch 16-byte aligned
+            off += (size + 31) & ~31     # 256-byte aligned, as the server's pool ring places them
         tuned = rngx.get_batch_cfg()
         rngx.set_batch_cfg(256, 4, 0, False, 16, 1, False)
         try:
@@ -414,19 +414,21 @@ def cpu_baseline(n_total, iters, min_seconds=10.0, single_seconds=5.0):
     return res
 
 
-def trace_summary(path, match, split_ms):
+def trace_summary(path, match, split_ms, queues=None):
     """Device occupancy of the kernels whose names contain `match`, from a
     rocprofv3 kernel trace (the SQLite results database): the dispatches are
     cut into runs wherever the device stays idle longer than `split_ms`; per
     run, the span from the first start to the last end, the busy time (union
     of the kernels' intervals), the idle gaps between busy periods, and the
-    mean number of kernels in flight."""
+    mean number of kernels in flight. `queues`: only dispatches on these
+    hardware queue ids (all if None)."""
     import sqlite3
     db = sqlite3.connect(path)
     cols = [r[1] for r in db.execute("pragma table_info(kernels)")]
     end = "end" if "end" in cols else "start + duration"
     rows = db.execute('select name, start, %s, queue_id from kernels order by start' % end).fetchall()
-    ks = [(int(a), int(b), q) for nm, a, b, q in rows if match in nm]
+    ks = [(int(a), int(b), q) for nm, a, b, q in rows
+          if match in nm and (queues is None or q in queues)]
     runs, cur, reach = [], [], 0
     for a, b, q in ks:
         if cur and a - reach > split_ms * 1e6:
@@ -491,10 +493,12 @@ def main():
                     help="with --trace-summary: kernels whose names contain this text")
     ap.add_argument("--trace-split-ms", type=float, default=5.0,
                     help="with --trace-summary: idle time that separates two runs")
+    ap.add_argument("--trace-queues", type=lambda v: {int(x) for x in v.split(",")},
+                    help="with --trace-summary: comma-separated hardware queue ids")
     args = ap.parse_args()
     if args.trace_summary:
         for i, run in enumerate(trace_summary(args.trace_summary, args.trace_kernels,
-                                              args.trace_split_ms)):
+                                              args.trace_split_ms, args.trace_queues)):
             print(json.dumps(dict(run=i, **run)), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))

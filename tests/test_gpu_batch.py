@@ -75,6 +75,32 @@ def test_small_tables_in_kernel_arguments(oracle, m, S):
         assert np.array_equal(_run(_reqs(r), r.total), exp), row
 
 
+@pytest.mark.parametrize("entry", ["generate_batch", "generate_batch_noalloc"])
+@pytest.mark.parametrize("cfg", [dict(values_per_lane=256, waves_per_block=4, blocks=0,
+                                      use_graph=True, row_values=16, run_items=1),
+                                 dict(values_per_lane=64, waves_per_block=2, blocks=0,
+                                      use_graph=False, row_values=16, run_items=1,
+                                      per_item=True),
+                                 dict(values_per_lane=128, waves_per_block=4, blocks=50,
+                                      use_graph=False, row_values=8, run_items=8)],
+                         ids=["persistent", "per-item", "runs-rows8"])
+def test_output_at_every_16_byte_offset_of_a_line(oracle, entry, cfg):
+    # The packed output may start anywhere 16-byte aligned; its tiles are
+    # laid on its 128-byte lines, whatever its offset in the line.
+    r = inputs.ragged_requests(m=29, seed=77, max_len=90000, max_offset=3000)
+    exp = oracle.generate_batch(_oracle_reqs(oracle, r))
+    rngx.set_batch_cfg(**cfg)
+    buf = torch.zeros(r.total + 32, dtype=torch.int64, device="cuda")
+    assert buf.data_ptr() % 128 == 0
+    for skew in range(0, 16, 2):
+        buf.zero_()
+        getattr(rngx, entry)(_reqs(r), buf[skew:skew + r.total])
+        torch.cuda.synchronize()
+        host = buf.cpu().numpy().view(np.uint64)
+        assert not host[:skew].any() and not host[skew + r.total:].any(), skew
+        assert np.array_equal(host[skew:skew + r.total], exp), skew
+
+
 def test_per_item_graph_follows_item_count(oracle):
     # The captured graph is re-captured when the item count changes and
     # reused when it does not; every replay checked against the oracle.
