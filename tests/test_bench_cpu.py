@@ -31,3 +31,34 @@ def test_help_lists_the_modes():
     for flag in ("--steps", "--warmup", "--batched-only", "--serving-only", "--streaming-only",
                  "--copy-probe", "--placement-probe"):
         assert flag in r.stdout
+
+
+def test_trace_summary_of_a_synthetic_kernel_trace(tmp_path):
+    # A rocprofv3-shaped `kernels` table: two overlapping batches on two
+    # queues, a gap, a third batch; a run break; a kernel on another queue.
+    import json
+    import sqlite3
+    db = tmp_path / "t_results.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, start int, end int, duration int, queue_id int)")
+    rows = [("batch_kernel", 0, 100_000, 3), ("batch_kernel", 50_000, 150_000, 4),
+            ("batch_kernel", 160_000, 200_000, 3), ("gen_kernel", 0, 10, 2),
+            ("batch_kernel", 20_000_000, 20_100_000, 3), ("batch_kernel", 20_100_000, 20_200_000, 4),
+            ("batch_kernel", 30_000_000, 30_050_000, 2)]
+    for name, a, b, q in rows:
+        con.execute("insert into kernels values (?,?,?,?,?)", (name, a, b, b - a, q))
+    con.commit()
+    con.close()
+    r = _bench("--trace-summary", str(db), "--trace-kernels", "batch", "--trace-queues", "3,4")
+    assert r.returncode == 0, r.stderr
+    runs = [json.loads(l) for l in r.stdout.splitlines()]
+    assert len(runs) == 2
+    a, b = runs
+    assert a["kernels"] == 3 and a["queues"] == [3, 4]
+    assert a["span_ms"] == 0.2 and a["busy_ms"] == 0.19 and a["gaps"] == 1
+    assert a["gap_max_us"] == 10.0 and a["kernel_sum_ms"] == 0.24
+    assert a["mean_in_flight"] == round(0.24 / 0.19, 3)
+    assert b["kernels"] == 2 and b["busy_frac"] == 1.0 and b["gaps"] == 0
+    # Without the queue filter the queue-2 batch forms a third run.
+    r = _bench("--trace-summary", str(db))
+    assert [json.loads(l)["kernels"] for l in r.stdout.splitlines()] == [3, 2, 1]
