@@ -463,6 +463,46 @@ def trace_summary(path, match, split_ms, queues=None):
     return out
 
 
+def trace_overlap(path, name_a, name_b):
+    """From a rocprofv3 kernel trace: for kernels whose names contain
+    `name_a` and `name_b`, their counts per hardware queue, total durations,
+    and the time kernels of the first kind ran while a kernel of the second
+    kind was running (overlap with the union of the second kind's
+    intervals)."""
+    import bisect
+    import sqlite3
+    db = sqlite3.connect(path)
+    cols = [r[1] for r in db.execute("pragma table_info(kernels)")]
+    end = "end" if "end" in cols else "start + duration"
+    rows = db.execute("select name, start, %s, queue_id from kernels order by start" % end).fetchall()
+    A = [(int(a), int(b), q) for nm, a, b, q in rows if name_a in nm]
+    B = [(int(a), int(b), q) for nm, a, b, q in rows if name_b in nm]
+    merged = []
+    for a, b, _ in B:
+        if merged and a <= merged[-1][1]:
+            merged[-1][1] = max(merged[-1][1], b)
+        else:
+            merged.append([a, b])
+    starts = [m[0] for m in merged]
+    overlap = 0
+    for a, b, _ in A:
+        i = max(0, bisect.bisect_right(starts, a) - 1)
+        while i < len(merged) and merged[i][0] < b:
+            overlap += max(0, min(b, merged[i][1]) - max(a, merged[i][0]))
+            i += 1
+
+    def per_queue(K):
+        out = {}
+        for _, _, q in K:
+            out[str(q)] = out.get(str(q), 0) + 1
+        return out
+    return {"a": name_a, "a_kernels": len(A), "a_queues": per_queue(A),
+            "a_total_ms": round(sum(b - a for a, b, _ in A) / 1e6, 3),
+            "b": name_b, "b_kernels": len(B), "b_queues": per_queue(B),
+            "b_total_ms": round(sum(b - a for a, b, _ in B) / 1e6, 3),
+            "overlap_ms": round(overlap / 1e6, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -495,7 +535,12 @@ def main():
                     help="with --trace-summary: idle time that separates two runs")
     ap.add_argument("--trace-queues", type=lambda v: {int(x) for x in v.split(",")},
                     help="with --trace-summary: comma-separated hardware queue ids")
+    ap.add_argument("--trace-overlap", nargs=3, metavar=("RESULTS_DB", "NAME_A", "NAME_B"),
+                    help="only report how long kernels named NAME_A ran while NAME_B kernels ran")
     args = ap.parse_args()
+    if args.trace_overlap:
+        print(json.dumps(trace_overlap(*args.trace_overlap)), flush=True)
+        return
     if args.trace_summary:
         for i, run in enumerate(trace_summary(args.trace_summary, args.trace_kernels,
                                               args.trace_split_ms, args.trace_queues)):

@@ -62,3 +62,28 @@ def test_trace_summary_of_a_synthetic_kernel_trace(tmp_path):
     # Without the queue filter the queue-2 batch forms a third run.
     r = _bench("--trace-summary", str(db))
     assert [json.loads(l)["kernels"] for l in r.stdout.splitlines()] == [3, 2, 1]
+
+
+def test_trace_overlap_of_a_synthetic_kernel_trace(tmp_path):
+    import json
+    import sqlite3
+    db = tmp_path / "o_results.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, start int, end int, duration int, queue_id int)")
+    us = 1000
+    rows = [("gen_kernel", 0, 10 * us, 1), ("d2h_kernel", 5 * us, 20 * us, 2),
+            ("gen_kernel", 20 * us, 30 * us, 1), ("d2h_kernel", 25 * us, 40 * us, 2),
+            ("d2h_kernel", 39 * us, 45 * us, 3), ("gen_kernel", 42 * us, 50 * us, 1),
+            ("gen_kernel", 100 * us, 110 * us, 1)]
+    for name, a, b, q in rows:
+        con.execute("insert into kernels values (?,?,?,?,?)", (name, a, b, b - a, q))
+    con.commit()
+    con.close()
+    r = _bench("--trace-overlap", str(db), "gen_kernel", "d2h_kernel")
+    assert r.returncode == 0, r.stderr
+    d = json.loads(r.stdout)
+    assert d["a_kernels"] == 4 and d["a_queues"] == {"1": 4}
+    assert d["b_kernels"] == 3 and d["b_queues"] == {"2": 2, "3": 1}
+    assert d["a_total_ms"] == 0.038 and d["b_total_ms"] == 0.036
+    # 5 + 5 + 3 us: the last two copies overlap each other and count once.
+    assert d["overlap_ms"] == 0.013
