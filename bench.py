@@ -503,6 +503,29 @@ def trace_overlap(path, name_a, name_b):
             "overlap_ms": round(overlap / 1e6, 3)}
 
 
+def trace_stats(path):
+    """Per (kernel name, hardware queue) of a rocprofv3 kernel trace: the
+    number of dispatches and their total, mean, p50, p99 and largest
+    durations in microseconds."""
+    import sqlite3
+    db = sqlite3.connect(path)
+    cols = [r[1] for r in db.execute("pragma table_info(kernels)")]
+    end = "end" if "end" in cols else "start + duration"
+    groups = {}
+    for nm, a, b, q in db.execute("select name, start, %s, queue_id from kernels" % end):
+        groups.setdefault((nm, q), []).append(int(b) - int(a))
+    out = []
+    for (nm, q), d in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        d.sort()
+        pick = lambda p: d[min(len(d) - 1, int(p * len(d)))] / 1e3
+        short = nm.replace("(anonymous namespace)::", "").split("(")[0]
+        out.append({"kernel": short, "queue": q, "calls": len(d),
+                    "total_us": round(sum(d) / 1e3, 1), "mean_us": round(sum(d) / len(d) / 1e3, 2),
+                    "p50_us": round(pick(0.5), 2), "p99_us": round(pick(0.99), 2),
+                    "max_us": round(d[-1] / 1e3, 2)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -537,7 +560,13 @@ def main():
                     help="with --trace-summary: comma-separated hardware queue ids")
     ap.add_argument("--trace-overlap", nargs=3, metavar=("RESULTS_DB", "NAME_A", "NAME_B"),
                     help="only report how long kernels named NAME_A ran while NAME_B kernels ran")
+    ap.add_argument("--trace-stats", metavar="RESULTS_DB",
+                    help="only list dispatch counts and durations per kernel and queue")
     args = ap.parse_args()
+    if args.trace_stats:
+        for row in trace_stats(args.trace_stats):
+            print(json.dumps(row), flush=True)
+        return
     if args.trace_overlap:
         print(json.dumps(trace_overlap(*args.trace_overlap)), flush=True)
         return

@@ -87,3 +87,24 @@ def test_trace_overlap_of_a_synthetic_kernel_trace(tmp_path):
     assert d["a_total_ms"] == 0.038 and d["b_total_ms"] == 0.036
     # 5 + 5 + 3 us: the last two copies overlap each other and count once.
     assert d["overlap_ms"] == 0.013
+
+
+def test_trace_stats_of_a_synthetic_kernel_trace(tmp_path):
+    import json
+    import sqlite3
+    db = tmp_path / "s_results.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, start int, end int, duration int, queue_id int)")
+    name = "void rngx::(anonymous namespace)::batch_kernel<256, 16, false>(rngx::BatchDesc const*)"
+    for i, d in enumerate([1000, 2000, 3000, 4000]):
+        con.execute("insert into kernels values (?,?,?,?,?)", (name, 10**6 * i, 10**6 * i + d, d, 3))
+    con.execute("insert into kernels values (?,?,?,?,?)", ("init_kernel(unsigned long*)", 0, 500, 500, 1))
+    con.commit()
+    con.close()
+    r = _bench("--trace-stats", str(db))
+    assert r.returncode == 0, r.stderr
+    rows = [json.loads(l) for l in r.stdout.splitlines()]
+    assert rows[0] == {"kernel": "void rngx::batch_kernel<256, 16, false>", "queue": 3, "calls": 4,
+                       "total_us": 10.0, "mean_us": 2.5, "p50_us": 3.0, "p99_us": 4.0,
+                       "max_us": 4.0}
+    assert rows[1]["kernel"] == "init_kernel" and rows[1]["calls"] == 1
