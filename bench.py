@@ -91,17 +91,25 @@ def plain_run(torch, rngx, seed, n, iters, u32, warmup, steps, out=None):
 
 
 def sweep(torch, rngx, reps):
-    """HBM roofline sweep: n in 2^20..2^26, 256 iterations, seeds 1..4, u64 and u32."""
+    """HBM roofline sweep: n in 2^20..2^26 x 256 iterations x seeds 1..4 x
+    u64 and u32 (32 runs), output kept in HBM; one output buffer per size
+    and word type, shared by its four seeds."""
     from paper_1609_01257_amd import inputs
     rows = []
-    for n, seed in zip(inputs.ROOFLINE_N, inputs.ROOFLINE_SEEDS):
+    iters = inputs.ROOFLINE_ITERS
+    for n in inputs.ROOFLINE_N:
         for u32 in (False, True):
-            r = plain_run(torch, rngx, seed, n, inputs.ROOFLINE_ITERS, u32, 1, reps)
-            rows.append({"n": n, "seed": seed, "dtype": "u32" if u32 else "u64",
-                         "kernel_gbs": round(r["kernel_gbs"], 1),
-                         "out_gbs": round(r["out_gbs"], 1),
-                         "frac_hbm": round(r["kernel_gbs"] / HBM_PEAK_GBS, 4)})
-            log("sweep", rows[-1])
+            out = torch.empty(n * iters, dtype=torch.int32 if u32 else torch.int64,
+                              device="cuda")
+            for seed in inputs.ROOFLINE_SEEDS:
+                r = plain_run(torch, rngx, seed, n, iters, u32, 1, reps, out=out)
+                rows.append({"n": n, "seed": seed, "dtype": "u32" if u32 else "u64",
+                             "kernel_gbs": round(r["kernel_gbs"], 1),
+                             "out_gbs": round(r["out_gbs"], 1),
+                             "frac_hbm": round(r["kernel_gbs"] / HBM_PEAK_GBS, 4)})
+                log("sweep", rows[-1])
+            del out
+            torch.cuda.empty_cache()
     return rows
 
 
