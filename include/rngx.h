@@ -442,8 +442,8 @@ int rngx_jump_ahead(uint64_t state, uint64_t k, uint64_t *out);
  * pool: caller-owned device memory of pool_bytes bytes, 256-byte aligned,
  *       kept alive until rngx_serve_stop; results are written into it.
  * Batches are launched directly (no graph) with a schedule chosen by their
- * size, independent of the batch configuration: up to 2^20 values, one wave
- * per 4,096-value item (tables of up to 16 requests in the kernel's
+ * size, independent of the batch configuration: up to 2^23 values, one wave
+ * per 1,024-value item (tables of up to 16 requests in the kernel's
  * arguments); larger, the persistent grid with 256 values per lane, at most
  * 8 waves per compute unit, fitted to the batch.
  * Errors: RNGX_E_BUSY if already running; RNGX_E_INVAL (n_states == 0, NULL
