@@ -25,16 +25,29 @@ sys.path.insert(0, ROOT)
 METRIC = "RNG output GB/s (% HBM peak), batched vs plain; p50/p99 request latency"
 HBM_PEAK_GBS = 8000.0
 GIB = 1 << 30
+# The library's default plain launches (block, chunks, non-temporal,
+# pace_gbs); u32 block 0 = chosen by size.
+LIB_DEFAULT_U64 = (512, 4, 0, 0)
+LIB_DEFAULT_U32 = (0, 0, 0, 0)
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def launch_key(launch):
+    """What selects the kernel code of a plain launch: chunks, non-temporal
+    stores, scheduled or not (block and the schedule's rate are launch
+    parameters of the same code)."""
+    return (int(launch["chunks"]), int(bool(launch["nontemporal"])),
+            int(launch["pace_gbs"] > 0))
+
+
 def counter_traffic(launch):
     """HBM bytes per launch of the headline kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source
-    or its launch configuration changed since those counters were taken."""
+    changed since those counters were taken or `launch` selects other kernel
+    code than the launch they were taken with."""
     import hashlib
     src = os.path.join(ROOT, "paper_1609_01257_amd", "csrc", "kernels.hip")
     summary = os.path.join(ROOT, "profiles", "gen_kernel_u64_2p26x256.md")
@@ -44,8 +57,12 @@ def counter_traffic(launch):
         return None
     kv = dict(tok.split("=", 1) for tok in line.split()[1:])
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    cfg = "%d,%d,%d" % (launch["block"], launch["chunks"], int(launch["nontemporal"]))
-    if kv.get("kernels_hip_sha256_16") != digest or kv.get("launch") != cfg:
+    try:
+        b, c, nt, pace = (int(x) for x in kv.get("launch", "").split(","))
+    except ValueError:
+        return None
+    taken = {"block": b, "chunks": c, "nontemporal": nt, "pace_gbs": pace}
+    if kv.get("kernels_hip_sha256_16") != digest or launch_key(taken) != launch_key(launch):
         return None
     return int(kv["traffic_bytes_per_launch"])
 
@@ -93,23 +110,39 @@ def plain_run(torch, rngx, seed, n, iters, u32, warmup, steps, out=None):
 def sweep(torch, rngx, reps):
     """HBM roofline sweep: n in 2^20..2^26 x 256 iterations x seeds 1..4 x
     u64 and u32 (32 runs), output kept in HBM; one output buffer per size
-    and word type, shared by its four seeds."""
+    and word type, shared by its four seeds. Each buffer is first timed at
+    the library's default launch (seed 1, `default_gbs`), then the launch autotuner
+    picks a configuration on it (`launch`, with row schedules among the
+    candidates) and the four seeds run with that one."""
     from paper_1609_01257_amd import inputs
     rows = []
     iters = inputs.ROOFLINE_ITERS
-    for n in inputs.ROOFLINE_N:
-        for u32 in (False, True):
-            out = torch.empty(n * iters, dtype=torch.int32 if u32 else torch.int64,
-                              device="cuda")
-            for seed in inputs.ROOFLINE_SEEDS:
-                r = plain_run(torch, rngx, seed, n, iters, u32, 1, reps, out=out)
-                rows.append({"n": n, "seed": seed, "dtype": "u32" if u32 else "u64",
-                             "kernel_gbs": round(r["kernel_gbs"], 1),
-                             "out_gbs": round(r["out_gbs"], 1),
-                             "frac_hbm": round(r["kernel_gbs"] / HBM_PEAK_GBS, 4)})
-                log("sweep", rows[-1])
-            del out
-            torch.cuda.empty_cache()
+    saved = (rngx.get_launch(False), rngx.get_launch(True))
+    try:
+        for n in inputs.ROOFLINE_N:
+            for u32 in (False, True):
+                out = torch.empty(n * iters, dtype=torch.int32 if u32 else torch.int64,
+                                  device="cuda")
+                rngx.set_launch(u32, *(LIB_DEFAULT_U32 if u32 else LIB_DEFAULT_U64))
+                base = plain_run(torch, rngx, inputs.ROOFLINE_SEEDS[0], n, iters, u32, 1, reps,
+                                 out=out)
+                # At least about 8 GiB of timed output per candidate.
+                tune_reps = max(2, (8 * GIB) // (n * iters * (4 if u32 else 8)))
+                tune = rngx.autotune_plain(iters, out, reps=tune_reps, u32=u32)
+                for seed in inputs.ROOFLINE_SEEDS:
+                    r = plain_run(torch, rngx, seed, n, iters, u32, 1, reps, out=out)
+                    rows.append({"n": n, "seed": seed, "dtype": "u32" if u32 else "u64",
+                                 "kernel_gbs": round(r["kernel_gbs"], 1),
+                                 "out_gbs": round(r["out_gbs"], 1),
+                                 "frac_hbm": round(r["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                                 "launch": tune["best"],
+                                 "default_gbs": round(base["kernel_gbs"], 1)})
+                    log("sweep", rows[-1])
+                del out
+                torch.cuda.empty_cache()
+    finally:
+        rngx.set_launch(False, **saved[0])
+        rngx.set_launch(True, **saved[1])
     return rows
 
 
@@ -547,6 +580,12 @@ def main():
                     help="run only the headline kernel (for profiling)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched ragged-stream step (for profiling)")
+    ap.add_argument("--launch", metavar="B,C,NT,PACE",
+                    type=lambda v: tuple(int(x) for x in v.split(",")),
+                    help="plain launch configuration of the headline (block, chunks, "
+                         "non-temporal, pace_gbs) instead of the autotuner's choice")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="run only the roofline sweep with its per-buffer autotuning")
     ap.add_argument("--streaming-only", action="store_true",
                     help="run only the paper-shaped streaming pipeline (for profiling)")
     ap.add_argument("--serving-only", action="store_true",
@@ -647,6 +686,11 @@ def main():
         rngx.shutdown()
         print(json.dumps({"batched": res}), flush=True)
         return
+    if args.sweep_only:
+        res = sweep(torch, rngx, 3)
+        rngx.shutdown()
+        print(json.dumps({"sweep": res}), flush=True)
+        return
     if args.streaming_only:
         res = streaming(torch, rngx)
         log("streaming:", res)
@@ -661,8 +705,27 @@ def main():
         print(json.dumps({"serving": res}), flush=True)
         return
     n, iters, seed = 1 << 26, 256, 1
-    log("headline: plain u64, n=2^26, iters=256, warmup=%d steps=%d" % (args.warmup, args.steps))
-    head = plain_run(torch, rngx, seed, n, iters, False, args.warmup, args.steps)
+    out = torch.empty(n * iters, dtype=torch.int64, device="cuda")
+    default_launch = rngx.get_launch(False)
+    base = tune = None
+    if args.launch:
+        rngx.set_launch(False, *args.launch)
+    else:
+        # The library's default launch, then its launch autotuner on the
+        # headline buffer (before the timed steps; the timed steps then run
+        # the chosen configuration).
+        log("headline: default launch", default_launch)
+        base = plain_run(torch, rngx, seed, n, iters, False, 1, 3, out=out)
+        log("headline, default launch:", base)
+        rngx.init(seed, n)
+        tune = rngx.autotune_plain(iters, out, reps=2)
+        log("autotune best:", tune["best"], "%.3f ms" % tune["best_ms"])
+    launch = rngx.get_launch(False)
+    log("headline: plain u64, n=2^26, iters=256, warmup=%d steps=%d, launch %s"
+        % (args.warmup, args.steps, launch))
+    head = plain_run(torch, rngx, seed, n, iters, False, args.warmup, args.steps, out=out)
+    del out
+    torch.cuda.empty_cache()
     log("headline:", head)
     result = {
         "metric": METRIC,
@@ -680,22 +743,36 @@ def main():
         "config": {"workload": "plain generator, 2^26 streams x 256 iterations of uint64 "
                                "(128 GiB per step), seed 1, output kept in HBM",
                    "n_states": n, "iters": iters, "seed": seed,
-                   "launch": rngx.get_launch(False)},
+                   "launch": launch,
+                   "launch_source": "--launch" if args.launch else
+                   "rngx_autotune_plain on the headline buffer before the timed steps "
+                   "(%d candidates)" % len(tune["tried"])},
         "roofline": {"bound": "hbm",
                      "achieved": round(head["kernel_gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(head["kernel_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": counter_traffic(rngx.get_launch(False)),
-                     "kernel": "gen_kernel<u64>",
+                     "traffic": counter_traffic(launch),
+                     "kernel": "gen_paced_kernel<u64>" if launch["pace_gbs"] else "gen_kernel<u64>",
                      "kernel_avg_ms": round(head["kernel_avg_s"] * 1e3, 4),
                      "alg_bytes_per_launch": head["alg_bytes_per_launch"]},
     }
+    if base is not None:
+        result["default_launch"] = {"launch": default_launch,
+                                    "kernel_gbs": round(base["kernel_gbs"], 1),
+                                    "frac_hbm": round(base["kernel_gbs"] / HBM_PEAK_GBS, 4)}
     if not args.headline_only:
         log("u32 headline shape")
-        h32 = plain_run(torch, rngx, seed, n, iters, True, 1, max(3, args.steps // 4))
+        out32 = torch.empty(n * iters, dtype=torch.int32, device="cuda")
+        if not args.launch:
+            rngx.init(seed, n)
+            rngx.autotune_plain(iters, out32, reps=2, u32=True)
+        h32 = plain_run(torch, rngx, seed, n, iters, True, 1, max(3, args.steps // 4), out=out32)
+        del out32
+        torch.cuda.empty_cache()
         result["u32"] = {"out_gbs": round(h32["out_gbs"], 1),
                          "kernel_gbs": round(h32["kernel_gbs"], 1),
-                         "frac_hbm": round(h32["kernel_gbs"] / HBM_PEAK_GBS, 4)}
+                         "frac_hbm": round(h32["kernel_gbs"] / HBM_PEAK_GBS, 4),
+                         "launch": rngx.get_launch(True)}
         log("scrambled variant, headline shape")
         rngx.set_scrambler(rngx.SCRAMBLE_STAR)
         try:

@@ -152,14 +152,28 @@ int rngx_hip_notes(uint64_t *released, uint64_t *stray, char *text, size_t cap, 
  *         owns 2*chunks (u64) or 4*chunks (u32) work-items, and every store
  *         instruction of a wavefront covers 1 KiB of contiguous output.
  * nontemporal: 1 to use non-temporal (streaming) stores.
- * Defaults: u64 block 512, 4 chunks, normal stores; u32 the library's
- * choice (measured on MI355X: block 256 with 4 chunks up to 2^20 states,
- * block 512 with 4 chunks below 2^26, block 512 with 2 chunks from 2^26).
+ * pace_gbs: 0, or a row schedule for the launch, 1000..20000 (GB/s). With a
+ *         schedule the kernel runs on a persistent grid of every block that
+ *         fits on the device at once, the blocks walking strips of columns
+ *         in turn, and every wavefront writes its iteration k of strip s
+ *         no earlier than its own start time + (s * n_iters + k) times the
+ *         time the resident wavefronts' share of a row takes at pace_gbs,
+ *         read from the device's constant-rate clock. Wavefronts ahead of
+ *         the schedule wait; those behind run freely, so the grid moves
+ *         down the rows together instead of drifting apart (each wait is
+ *         bounded; the schedule never changes a value). Used for calls of
+ *         at least 2 iterations on 16-byte aligned rows; other calls run
+ *         the unscheduled kernel.
+ * Defaults: u64 block 512, 4 chunks, normal stores, no schedule; u32 the
+ * library's choice (measured on MI355X: block 256 with 4 chunks up to 2^20
+ * states, block 512 with 4 chunks below 2^26, block 512 with 2 chunks from
+ * 2^26). The autotuner (rngx_autotune_plain) also tries schedules.
  * The output never depends on the configuration. */
 typedef struct rngx_launch {
     uint32_t block;
     uint32_t chunks;
     uint32_t nontemporal;
+    uint32_t pace_gbs;
 } rngx_launch;
 
 /* Set the configuration used by rngx_generate (u32 != 0: rngx_generate_u32).
@@ -369,15 +383,20 @@ int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_
 /* Autotuner of the plain generator's launch configuration (the batched
  * autotuner's counterpart, for rngx_generate / rngx_generate_u32): time
  * every configuration block {256, 512, 1024} x chunks {1, 2, 4} x
- * nontemporal {0, 1} on the current generator (its n_states) for n_iters
- * iterations on `stream`, with HIP events around each launch; every
- * candidate starts from a snapshot of the states, so all of them write the
+ * nontemporal {0, 1} (18 bases), then row schedules (pace_gbs): every
+ * base at 6000, 6750 and 7500 GB/s, and the two bases fastest with a
+ * schedule at 5500..8000 GB/s in steps of 250 (88 candidates in all), on
+ * the current generator (its n_states) for n_iters
+ * iterations on `stream`, with HIP events around each candidate's timed
+ * launches; every candidate starts from a snapshot of the states, so all
+ * of them write the
  * same values, V(seed, g, cursor + k) for k < n_iters, which is checked by
  * checksum. The fastest becomes the launch configuration of that output type
  * (as rngx_set_launch would set it). On return `out` holds those values and
  * the generator's states and cursor are as before the call.
  * out: device memory of n_iters * n_states values (8-byte, or 4-byte with
- * u32, aligned). reps: timed launches per candidate (>= 1). The snapshot
+ * u32, aligned). reps: launches per candidate, run back to back and timed
+ * together (>= 1). The snapshot
  * (8 * n_states bytes) is allocated and freed by the call.
  * Errors: RNGX_E_NOINIT; RNGX_E_INVAL (NULL result or out, misaligned out,
  * reps or n_iters 0); RNGX_E_NOMEM; RNGX_E_HIP (also when two candidates

@@ -395,7 +395,7 @@ int rngx_set_launch(int u32, const rngx_launch *cfg)
     if (!cfg || (cfg->block != 0 && !launch_cfg_valid(*cfg)))
         return set_error(RNGX_E_INVAL,
                          "rngx_set_launch: block must be 0 (automatic) or 64..1024 in steps of "
-                         "64, chunks 1, 2 or 4, nontemporal 0 or 1");
+                         "64, chunks 1, 2 or 4, nontemporal 0 or 1, pace_gbs 0 or 1000..20000");
     (u32 ? c.cfg32 : c.cfg64) = *cfg;
     return RNGX_OK;
 }

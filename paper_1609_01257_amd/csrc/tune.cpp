@@ -10,6 +10,7 @@
 // JSON per (device, kind), kind = plain_u64, plain_u32 or batch. Lines are
 // written by this file only, in a fixed key order, and read back with a
 // small key lookup; any line that does not parse is an error naming it.
+#include <algorithm>
 #include <cerrno>
 #include <cstdio>
 #include <cstdlib>
@@ -42,11 +43,11 @@ struct CacheLine {
     double ms = 0.0;
 };
 
-const char *const kPlainKeys[3] = {"block", "chunks", "nontemporal"};
+const char *const kPlainKeys[4] = {"block", "chunks", "nontemporal", "pace_gbs"};
 const char *const kBatchKeys[7] = {"values_per_lane", "waves_per_block", "blocks", "use_graph",
                                    "row_values", "run_items", "per_item"};
 
-int n_keys(const std::string &kind) { return kind == "batch" ? 7 : 3; }
+int n_keys(const std::string &kind) { return kind == "batch" ? 7 : 4; }
 const char *const *keys_of(const std::string &kind)
 {
     return kind == "batch" ? kBatchKeys : kPlainKeys;
@@ -96,7 +97,14 @@ bool parse_line(const std::string &line, CacheLine *c)
     const char *const *keys = keys_of(c->kind);
     for (int i = 0; i < n_keys(c->kind); ++i) {
         double v = 0.0;
-        if (!get_number(line, keys[i], &v) || v < 0.0 || v > 4294967295.0 || v != (uint32_t)v)
+        // Lines written before plain launches had a schedule have no
+        // pace_gbs: no schedule.
+        if (!get_number(line, keys[i], &v)) {
+            if (std::strcmp(keys[i], "pace_gbs") != 0)
+                return false;
+            v = 0.0;
+        }
+        if (v < 0.0 || v > 4294967295.0 || v != (uint32_t)v)
             return false;
         c->v[i] = (uint32_t)v;
     }
@@ -242,7 +250,7 @@ extern "C" int rngx_tune_cache_load(const char *path, uint32_t *applied)
             const rngx_batch_cfg b{c.v[0], c.v[1], c.v[2], c.v[3], c.v[4], c.v[5], c.v[6]};
             rc = rngx_set_batch_cfg(&b);
         } else {
-            const rngx_launch l{c.v[0], c.v[1], c.v[2]};
+            const rngx_launch l{c.v[0], c.v[1], c.v[2], c.v[3]};
             rc = rngx_set_launch(c.kind == "plain_u32", &l);
         }
         if (rc)
@@ -271,7 +279,7 @@ extern "C" int rngx_tune_cache_save(const char *path)
         if (rc)
             return rc;
         c.kind = u32 ? "plain_u32" : "plain_u64";
-        const uint32_t v[3] = {l.block, l.chunks, l.nontemporal};
+        const uint32_t v[4] = {l.block, l.chunks, l.nontemporal, l.pace_gbs};
         std::memset(c.v, 0, sizeof c.v);
         std::memcpy(c.v, v, sizeof v);
         rc = merge_into_cache(path, c);
@@ -357,54 +365,101 @@ extern "C" int rngx_autotune_plain(uint32_t n_iters, int u32, void *out, uint32_
         RNGX_HIP(hipMemcpyAsync(g.state, sc.snap, state_bytes, hipMemcpyDeviceToDevice, s));
         return RNGX_OK;
     };
-    for (uint32_t bi = 0; bi < 3; ++bi) {
-        for (uint32_t ci = 0; ci < 3; ++ci) {
-            for (uint32_t nt = 0; nt < 2; ++nt) {
-                const rngx_launch cfg{blocks[bi], chunks[ci], nt};
-                // Warm-up, then the output check.
-                if ((rc = restore()))
-                    return rc;
-                take_stray_error("before an autotuned rng kernel launch");
-                RNGX_HIP(launch_gen(cfg, u32 != 0, star, g.state, g.n, n_iters, out, s));
-                uint64_t sum = 0;
-                rc = rngx_checksum(static_cast<const uint64_t *>(out), words, s, &sum);
-                if (rc)
-                    return rc;
-                if (!have_ref) {
-                    ref_sum = sum;
-                    have_ref = true;
-                } else if (sum != ref_sum) {
-                    return set_error(RNGX_E_HIP,
-                                     "autotune: configuration (block=%u, chunks=%u, nt=%u) "
-                                     "produced a different output",
-                                     cfg.block, cfg.chunks, cfg.nontemporal);
-                }
-                double total_ms = 0.0;
-                for (uint32_t r = 0; r < reps; ++r) {
-                    if ((rc = restore()))
-                        return rc;
-                    RNGX_HIP(hipEventRecord(sc.e0, s));
-                    RNGX_HIP(launch_gen(cfg, u32 != 0, star, g.state, g.n, n_iters, out, s));
-                    RNGX_HIP(hipEventRecord(sc.e1, s));
-                    RNGX_HIP(hipEventSynchronize(sc.e1));
-                    float ms = 0.f;
-                    RNGX_HIP(hipEventElapsedTime(&ms, sc.e0, sc.e1));
-                    total_ms += ms;
-                }
-                const double mean = total_ms / reps;
-                if (result->n_tried < RNGX_TUNE_MAX) {
-                    result->tried[result->n_tried].cfg = cfg;
-                    result->tried[result->n_tried].ms = mean;
-                }
-                ++result->n_tried;
-                if (mean < best) {
-                    best = mean;
-                    result->best = cfg;
-                }
-            }
+    // One candidate: warm-up, output check against the first candidate's
+    // checksum, then `reps` launches back to back from the snapshot, timed
+    // together (as a caller's consecutive calls run); the mean in *ms.
+    auto try_cfg = [&](const rngx_launch &cfg, double *ms) -> int {
+        int rc2 = restore();
+        if (rc2)
+            return rc2;
+        take_stray_error("before an autotuned rng kernel launch");
+        RNGX_HIP(launch_gen(cfg, u32 != 0, star, g.state, g.n, n_iters, out, s));
+        uint64_t sum = 0;
+        rc2 = rngx_checksum(static_cast<const uint64_t *>(out), words, s, &sum);
+        if (rc2)
+            return rc2;
+        if (!have_ref) {
+            ref_sum = sum;
+            have_ref = true;
+        } else if (sum != ref_sum) {
+            return set_error(RNGX_E_HIP,
+                             "autotune: configuration (block=%u, chunks=%u, nt=%u, pace=%u) "
+                             "produced a different output",
+                             cfg.block, cfg.chunks, cfg.nontemporal, cfg.pace_gbs);
+        }
+        if ((rc2 = restore()))
+            return rc2;
+        RNGX_HIP(hipEventRecord(sc.e0, s));
+        for (uint32_t r = 0; r < reps; ++r)
+            RNGX_HIP(launch_gen(cfg, u32 != 0, star, g.state, g.n, n_iters, out, s));
+        RNGX_HIP(hipEventRecord(sc.e1, s));
+        RNGX_HIP(hipEventSynchronize(sc.e1));
+        float t = 0.f;
+        RNGX_HIP(hipEventElapsedTime(&t, sc.e0, sc.e1));
+        const double mean = (double)t / reps;
+        if (result->n_tried < RNGX_TUNE_MAX) {
+            result->tried[result->n_tried].cfg = cfg;
+            result->tried[result->n_tried].ms = mean;
+        }
+        ++result->n_tried;
+        if (mean < best) {
+            best = mean;
+            result->best = cfg;
+        }
+        *ms = mean;
+        return RNGX_OK;
+    };
+    // Unscheduled launches: block x chunks x non-temporal (18 bases).
+    constexpr int kBases = 18;
+    rngx_launch base[kBases];
+    for (uint32_t bi = 0, i = 0; bi < 3; ++bi)
+        for (uint32_t ci = 0; ci < 3; ++ci)
+            for (uint32_t nt = 0; nt < 2; ++nt, ++i)
+                base[i] = rngx_launch{blocks[bi], chunks[ci], nt, 0};
+    double ms = 0.0;
+    for (int i = 0; i < kBases; ++i)
+        if ((rc = try_cfg(base[i], &ms)))
+            return rc;
+    // Row schedules (they apply to aligned rows and calls of at least 2
+    // iterations; elsewhere the launch runs unscheduled). Which base and
+    // which rate suit a schedule is not predicted by the unscheduled times
+    // (measured), so: every base at 6000, 6750 and 7500 GB/s, then the two
+    // bases fastest with a schedule at 5500..8000 in steps of 250.
+    double sched_ms[kBases];
+    for (int i = 0; i < kBases; ++i) {
+        sched_ms[i] = 1e300;
+        for (uint32_t pace = 6000; pace <= 7500; pace += 750) {
+            if ((rc = try_cfg(rngx_launch{base[i].block, base[i].chunks, base[i].nontemporal,
+                                          pace},
+                              &ms)))
+                return rc;
+            sched_ms[i] = std::min(sched_ms[i], ms);
         }
     }
-    // Leave the generator exactly as it was (state and cursor).
+    int top[2] = {-1, -1};
+    for (int i = 0; i < kBases; ++i) {
+        if (top[0] < 0 || sched_ms[i] < sched_ms[top[0]]) {
+            top[1] = top[0];
+            top[0] = i;
+        } else if (top[1] < 0 || sched_ms[i] < sched_ms[top[1]]) {
+            top[1] = i;
+        }
+    }
+    for (int t : top) {
+        for (uint32_t pace = 5500; pace <= 8000; pace += 250) {
+            const bool tried = pace >= 6000 && pace <= 7500 && (pace - 6000) % 750 == 0;
+            if (!tried && (rc = try_cfg(rngx_launch{base[t].block, base[t].chunks,
+                                                    base[t].nontemporal, pace},
+                                        &ms)))
+                return rc;
+        }
+    }
+    // `out` gets the next n_iters iterations once more (the timed launches
+    // ran on from each other), with the chosen configuration; then the
+    // generator is left exactly as it was (state and cursor).
+    if ((rc = restore()))
+        return rc;
+    RNGX_HIP(launch_gen(result->best, u32 != 0, star, g.state, g.n, n_iters, out, s));
     if ((rc = restore()))
         return rc;
     RNGX_HIP(hipEventRecord(g.state_ready, s));
@@ -421,6 +476,7 @@ extern "C" int rngx_autotune_plain(uint32_t n_iters, int u32, void *out, uint32_
         c.v[0] = result->best.block;
         c.v[1] = result->best.chunks;
         c.v[2] = result->best.nontemporal;
+        c.v[3] = result->best.pace_gbs;
         c.ms = best;
         char buf[96];
         std::snprintf(buf, sizeof buf, "n=%u iters=%u", g.n, n_iters);

@@ -60,7 +60,7 @@ class TuneResult(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
-                ("nontemporal", ctypes.c_uint32)]
+                ("nontemporal", ctypes.c_uint32), ("pace_gbs", ctypes.c_uint32)]
 
 
 class PlainTuneEntry(ctypes.Structure):
@@ -439,7 +439,8 @@ def autotune_batch(reqs, out, reps=2, stream=None):
 
 
 def _launch_dict(c):
-    return {"block": c.block, "chunks": c.chunks, "nontemporal": bool(c.nontemporal)}
+    return {"block": c.block, "chunks": c.chunks, "nontemporal": bool(c.nontemporal),
+            "pace_gbs": c.pace_gbs}
 
 
 def autotune_plain(n_iters, out, reps=2, u32=False, stream=None):
@@ -581,15 +582,17 @@ def shutdown():
     _check(lib().rngx_shutdown())
 
 
-def set_launch(u32: bool, block: int, chunks: int, nontemporal: bool = False):
-    cfg = Launch(block, chunks, int(bool(nontemporal)))
+def set_launch(u32: bool, block: int, chunks: int, nontemporal: bool = False, pace_gbs: int = 0):
+    """Launch configuration of rngx_generate (u32: rngx_generate_u32); pace_gbs > 0
+    runs the row-scheduled persistent kernel at that write rate."""
+    cfg = Launch(block, chunks, int(bool(nontemporal)), pace_gbs)
     _check(lib().rngx_set_launch(int(u32), ctypes.byref(cfg)))
 
 
 def get_launch(u32: bool):
     cfg = Launch()
     _check(lib().rngx_get_launch(int(u32), ctypes.byref(cfg)))
-    return {"block": cfg.block, "chunks": cfg.chunks, "nontemporal": bool(cfg.nontemporal)}
+    return _launch_dict(cfg)
 
 
 # --- profiling ----------------------------------------------------------------

@@ -97,17 +97,24 @@ def test_scrambler_validation_without_gpu():
 
 
 def test_set_launch_validation():
-    for bad in [(32, 1, 0), (1088, 1, 0), (100, 1, 0), (256, 3, 0), (256, 0, 0), (256, 1, 2)]:
+    for bad in [(32, 1, 0), (1088, 1, 0), (100, 1, 0), (256, 3, 0), (256, 0, 0), (256, 1, 2),
+                (256, 1, 0, 999), (256, 1, 0, 20001)]:
         cfg = rngx.Launch(*bad)
         assert rngx.lib().rngx_set_launch(0, ctypes.byref(cfg)) == rngx.RNGX_E_INVAL
+    assert "pace_gbs" in rngx.last_error()
     rngx.set_launch(False, 512, 4, True)
-    assert rngx.get_launch(False) == {"block": 512, "chunks": 4, "nontemporal": True}
+    assert rngx.get_launch(False) == {"block": 512, "chunks": 4, "nontemporal": True,
+                                      "pace_gbs": 0}
+    rngx.set_launch(False, 256, 2, False, 6500)
+    assert rngx.get_launch(False) == {"block": 256, "chunks": 2, "nontemporal": False,
+                                      "pace_gbs": 6500}
     rngx.set_launch(False, 512, 4, False)
     # u32 defaults to the library's choice by size (block 0); it can be set
     # explicitly and back.
     assert rngx.get_launch(True)["block"] == 0
     rngx.set_launch(True, 256, 1, False)
-    assert rngx.get_launch(True) == {"block": 256, "chunks": 1, "nontemporal": False}
+    assert rngx.get_launch(True) == {"block": 256, "chunks": 1, "nontemporal": False,
+                                     "pace_gbs": 0}
     rngx.set_launch(True, 0, 0, False)
     assert rngx.get_launch(True)["block"] == 0
 
@@ -257,7 +264,8 @@ def test_tune_cache_errors_without_gpu(tmp_path):
     for bad in ['{"device": "x", "kind": "plain_u64", "block": 512}',
                 good.replace("plain_u64", "plain_u16"),
                 good.replace('"chunks": 4', '"chunks": 4.5'),
-                good.replace('"block": 512', '"block": -1')]:
+                good.replace('"block": 512', '"block": -1'),
+                good.replace('"nontemporal": 0', '"nontemporal": 0, "pace_gbs": -5')]:
         f = tmp_path / "c.jsonl"
         f.write_text(good + "\n" + bad + "\n")
         assert L.rngx_tune_cache_load(str(f).encode(), None) == rngx.RNGX_E_INVAL, bad

@@ -29,7 +29,7 @@ def test_help_lists_the_modes():
     r = _bench("--help")
     assert r.returncode == 0
     for flag in ("--steps", "--warmup", "--batched-only", "--serving-only", "--streaming-only",
-                 "--copy-probe", "--placement-probe"):
+                 "--copy-probe", "--placement-probe", "--sweep-only", "--launch"):
         assert flag in r.stdout
 
 
@@ -108,3 +108,32 @@ def test_trace_stats_of_a_synthetic_kernel_trace(tmp_path):
                        "total_us": 10.0, "mean_us": 2.5, "p50_us": 3.0, "p99_us": 4.0,
                        "max_us": 4.0}
     assert rows[1]["kernel"] == "init_kernel" and rows[1]["calls"] == 1
+
+
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_counter_traffic_matches_the_kernel_code_of_the_launch():
+    # The committed headline counters apply to launches that run the same
+    # kernel code (chunks, non-temporal stores, scheduled or not), whatever
+    # the block size or the schedule's rate, and to nothing else.
+    b = _bench_module()
+    line = [l for l in open(os.path.join(ROOT, "profiles", "gen_kernel_u64_2p26x256.md"))
+            if l.startswith("machine:")][0]
+    kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+    blk, ch, nt, pace = (int(x) for x in kv["launch"].split(","))
+    same = {"block": blk, "chunks": ch, "nontemporal": bool(nt), "pace_gbs": pace}
+    t = b.counter_traffic(same)
+    alg = 8 * (1 << 26) * 256 + 16 * (1 << 26)
+    assert t is not None and abs(t / alg - 1) < 1e-3
+    assert b.counter_traffic(dict(same, block=1024 if blk != 1024 else 256)) == t
+    if pace:
+        assert b.counter_traffic(dict(same, pace_gbs=pace + 250)) == t
+    assert b.counter_traffic(dict(same, pace_gbs=0 if pace else 7000)) is None
+    assert b.counter_traffic(dict(same, nontemporal=not nt)) is None
+    assert b.counter_traffic(dict(same, chunks=4 if ch != 4 else 1)) is None

@@ -79,7 +79,7 @@ def test_automatic_launch_choice(oracle, u32, n):
         exp = (oracle.generate_u32 if u32 else oracle.generate)(8, n, 2)
         assert np.array_equal(got, exp)
     finally:
-        rngx.set_launch(u32, default["block"], default["chunks"], default["nontemporal"])
+        rngx.set_launch(u32, **default)
 
 
 @pytest.mark.parametrize("u32", [False, True])
@@ -94,7 +94,57 @@ def test_every_launch_config_gives_identical_output(oracle, u32):
                 got = run(seed, n, iters, u32=u32, offset=offset)
                 assert np.array_equal(got, exp), (block, chunks, nt, offset)
     finally:
-        rngx.set_launch(u32, default["block"], default["chunks"], default["nontemporal"])
+        rngx.set_launch(u32, **default)
+
+
+# Row-scheduled (paced) launches: a persistent grid walking strips of
+# columns, every wavefront keeping to one row schedule. Shapes with 16-byte
+# aligned rows and a partial last wavefront; 1-wavefront blocks of one chunk
+# give several strips at these sizes; 1000 GB/s makes the waits long.
+PACED = [(False, 64, 1, 0, 1000, (1 << 21) + 6), (False, 512, 4, 0, 6500, (1 << 22) + 2050),
+         (False, 256, 2, 1, 3000, (1 << 21) + 1024), (True, 64, 1, 0, 2000, (1 << 21) + 4),
+         (True, 512, 4, 0, 6000, (1 << 22) + 8196)]
+
+
+@pytest.mark.parametrize("u32,block,chunks,nt,pace,n", PACED)
+def test_paced_launches_give_identical_output(oracle, u32, block, chunks, nt, pace, n):
+    iters, seed = 5, 4242
+    exp = (oracle.generate_u32 if u32 else oracle.generate)(seed, n, iters)
+    default = rngx.get_launch(u32)
+    try:
+        rngx.set_launch(u32, block, chunks, nt, pace)
+        assert np.array_equal(run(seed, n, iters, u32=u32), exp)
+        # Rows not 16-byte aligned, and single iterations, run unscheduled.
+        assert np.array_equal(run(seed, n, iters, u32=u32, offset=1), exp)
+        rngx.init(seed, n)
+        one = torch.empty(n, dtype=torch.int32 if u32 else torch.int64, device="cuda")
+        for k in range(2):
+            (rngx.generate_u32 if u32 else rngx.generate)(1, one)
+            torch.cuda.synchronize()
+            got = _u32(one) if u32 else _u64(one)
+            assert np.array_equal(got, exp[k]), k
+    finally:
+        rngx.set_launch(u32, **default)
+
+
+def test_paced_scrambled_and_continued_calls(oracle):
+    seed, n = 99, (1 << 21) + 2
+    default = rngx.get_launch(False)
+    try:
+        rngx.set_launch(False, 128, 2, False, 4000)
+        rngx.set_scrambler(rngx.SCRAMBLE_STAR)
+        rngx.init(seed, n)
+        a = torch.empty(3 * n, dtype=torch.int64, device="cuda")
+        b = torch.empty(4 * n, dtype=torch.int64, device="cuda")
+        rngx.generate(3, a)
+        rngx.generate(4, b)
+        torch.cuda.synchronize()
+        exp = oracle.generate_star(seed, n, 7)
+        assert np.array_equal(_u64(a).reshape(3, n), exp[:3])
+        assert np.array_equal(_u64(b).reshape(4, n), exp[3:])
+    finally:
+        rngx.set_scrambler(rngx.SCRAMBLE_NONE)
+        rngx.set_launch(False, **default)
 
 
 def test_cursor_continues_across_calls_and_widths(oracle):
@@ -292,7 +342,7 @@ def test_scrambled_every_launch_config(oracle, star, u32):
             rngx.set_launch(u32, block, chunks, nt)
             assert np.array_equal(run(seed, n, iters, u32=u32), exp), (block, chunks, nt)
     finally:
-        rngx.set_launch(u32, default["block"], default["chunks"], default["nontemporal"])
+        rngx.set_launch(u32, **default)
 
 
 def test_scrambler_switch_keeps_the_state_sequence(oracle):
@@ -326,12 +376,16 @@ def test_cursor_may_not_pass_the_last_value_number(oracle):
     assert rngx.lib().rngx_generate(1, out.data_ptr(), None) == rngx.RNGX_E_INVAL
 
 
+@pytest.mark.parametrize("n", [12345, 65540])
 @pytest.mark.parametrize("u32", [False, True])
-def test_plain_autotuner_keeps_state_and_output(oracle, u32):
+def test_plain_autotuner_keeps_state_and_output(oracle, u32, n):
     # Every candidate starts from the same snapshot: the tuner's output is
     # the next n_iters iterations, the cursor does not move, and the fastest
     # configuration becomes the launch configuration of that output type.
-    seed, n, iters = 9, 12345, 6
+    # 18 unscheduled bases, each base at 3 row schedules, then 8 more
+    # schedules on the two bases fastest with one (run scheduled at
+    # n = 65540, whose rows are 16-byte aligned).
+    seed, iters = 9, 6
     old = rngx.get_launch(u32)
     try:
         rngx.init(seed, n)
@@ -339,7 +393,21 @@ def test_plain_autotuner_keeps_state_and_output(oracle, u32):
         rngx.generate(3, pre)
         out = torch.zeros(iters * n + 1, dtype=torch.int32 if u32 else torch.int64, device="cuda")
         res = rngx.autotune_plain(iters, out, reps=1, u32=u32)
-        assert len(res["tried"]) == 18 and res["best_ms"] > 0
+        tried = res["tried"]
+        assert len(tried) == 88 and res["best_ms"] > 0
+        bases = [c for c, _ in tried[:18]]
+        assert all(c["pace_gbs"] == 0 for c in bases)
+        assert len({tuple(c.values()) for c in bases}) == 18
+        coarse = tried[18:72]
+        assert [c["pace_gbs"] for c, _ in coarse] == [6000, 6750, 7500] * 18
+        assert [{**c, "pace_gbs": 0} for c, _ in coarse[::3]] == bases
+        best_sched = [min(t for _, t in coarse[3 * i:3 * i + 3]) for i in range(18)]
+        top = sorted(range(18), key=lambda i: (best_sched[i], i))[:2]
+        fine = tried[72:]
+        fine_paces = [5500, 5750, 6250, 6500, 7000, 7250, 7750, 8000]
+        assert [c["pace_gbs"] for c, _ in fine] == fine_paces * 2
+        assert [{**c, "pace_gbs": 0} for c, _ in fine[::8]] == [bases[i] for i in top]
+        assert res["best"] == min(tried, key=lambda t: t[1])[0]
         assert rngx.get_launch(u32) == res["best"]
         assert rngx.info()[2] == 3
         exp = oracle.generate(seed, n, 3 + 2 * iters)
@@ -363,7 +431,7 @@ def test_tune_cache_roundtrip(tmp_path):
     old64, old32, oldb = rngx.get_launch(False), rngx.get_launch(True), rngx.get_batch_cfg()
     path = tmp_path / "tune.jsonl"
     try:
-        rngx.set_launch(False, 1024, 2, True)
+        rngx.set_launch(False, 1024, 2, True, 6250)
         rngx.set_launch(True, 256, 1, False)
         rngx.set_batch_cfg(128, 2, 77, False, 16, 8, False)
         rngx.tune_cache_save(path)
@@ -375,14 +443,18 @@ def test_tune_cache_roundtrip(tmp_path):
         rngx.set_launch(True, 512, 4, False)
         rngx.set_batch_cfg()
         assert rngx.tune_cache_load(path) == 3
-        assert rngx.get_launch(False) == {"block": 1024, "chunks": 2, "nontemporal": True}
-        assert rngx.get_launch(True) == {"block": 256, "chunks": 1, "nontemporal": False}
+        assert rngx.get_launch(False) == {"block": 1024, "chunks": 2, "nontemporal": True,
+                                          "pace_gbs": 6250}
+        assert rngx.get_launch(True) == {"block": 256, "chunks": 1, "nontemporal": False,
+                                         "pace_gbs": 0}
         assert rngx.get_batch_cfg() == {"values_per_lane": 128, "waves_per_block": 2,
                                         "blocks": 77, "use_graph": False, "row_values": 16,
                                         "run_items": 8, "per_item": False}
         rngx.tune_cache_save(path)
         lines = path.read_text().splitlines()
-        assert lines[0] == other and len(lines) == 4
+        # Kept, in the current form (a line without pace_gbs has no schedule).
+        assert lines[0] == other.replace('"nontemporal": 0,', '"nontemporal": 0, "pace_gbs": 0,')
+        assert len(lines) == 4
     finally:
         rngx.set_launch(False, **old64)
         rngx.set_launch(True, **old32)
