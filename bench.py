@@ -45,26 +45,27 @@ def launch_key(launch):
 
 def counter_traffic(launch):
     """HBM bytes per launch of the headline kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None if the kernel source
-    changed since those counters were taken or `launch` selects other kernel
-    code than the launch they were taken with."""
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (one `machine:` line per
+    launch measured), or None if the kernel source changed since those
+    counters were taken or none of them ran the kernel code `launch` selects."""
     import hashlib
     src = os.path.join(ROOT, "paper_1609_01257_amd", "csrc", "kernels.hip")
     summary = os.path.join(ROOT, "profiles", "gen_kernel_u64_2p26x256.md")
     try:
-        line = [l for l in open(summary) if l.startswith("machine:")][0]
-    except (OSError, IndexError):
+        lines = [l for l in open(summary) if l.startswith("machine:")]
+    except OSError:
         return None
-    kv = dict(tok.split("=", 1) for tok in line.split()[1:])
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    try:
-        b, c, nt, pace = (int(x) for x in kv.get("launch", "").split(","))
-    except ValueError:
-        return None
-    taken = {"block": b, "chunks": c, "nontemporal": nt, "pace_gbs": pace}
-    if kv.get("kernels_hip_sha256_16") != digest or launch_key(taken) != launch_key(launch):
-        return None
-    return int(kv["traffic_bytes_per_launch"])
+    for line in lines:
+        kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+        try:
+            b, c, nt, pace = (int(x) for x in kv.get("launch", "").split(","))
+        except ValueError:
+            continue
+        taken = {"block": b, "chunks": c, "nontemporal": nt, "pace_gbs": pace}
+        if kv.get("kernels_hip_sha256_16") == digest and launch_key(taken) == launch_key(launch):
+            return int(kv["traffic_bytes_per_launch"])
+    return None
 
 
 def kernel_avg_s(stats, name):
@@ -582,8 +583,9 @@ def main():
                     help="run only the batched ragged-stream step (for profiling)")
     ap.add_argument("--launch", metavar="B,C,NT,PACE",
                     type=lambda v: tuple(int(x) for x in v.split(",")),
-                    help="plain launch configuration of the headline (block, chunks, "
-                         "non-temporal, pace_gbs) instead of the autotuner's choice")
+                    help="plain launch configuration (block, chunks, non-temporal, pace_gbs) "
+                         "of the headline instead of the autotuner's choice, or of "
+                         "--plain-shape")
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the roofline sweep with its per-buffer autotuning")
     ap.add_argument("--streaming-only", action="store_true",
@@ -671,13 +673,17 @@ def main():
         return
     if args.plain_shape:
         n_s, it_s = args.plain_shape
-        log("plain %s, n=%d, iters=%d" % ("u32" if args.u32 else "u64", n_s, it_s))
+        if args.launch:
+            rngx.set_launch(args.u32, *args.launch)
+        log("plain %s, n=%d, iters=%d, launch %s" % ("u32" if args.u32 else "u64", n_s, it_s,
+                                                     rngx.get_launch(args.u32)))
+        launch = rngx.get_launch(args.u32)
         r = plain_run(torch, rngx, 1, n_s, it_s, args.u32, args.warmup, args.steps)
         r["frac_hbm"] = r["kernel_gbs"] / HBM_PEAK_GBS
         log("plain:", r)
         rngx.shutdown()
-        print(json.dumps({"plain": r, "n_states": n_s, "iters": it_s, "u32": args.u32}),
-              flush=True)
+        print(json.dumps({"plain": r, "n_states": n_s, "iters": it_s, "u32": args.u32,
+                          "launch": launch}), flush=True)
         return
     if args.batched_only:
         rngx.init(1, 64)          # opens the profiling window the step is timed in

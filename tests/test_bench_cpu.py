@@ -119,21 +119,28 @@ def _bench_module():
 
 
 def test_counter_traffic_matches_the_kernel_code_of_the_launch():
-    # The committed headline counters apply to launches that run the same
-    # kernel code (chunks, non-temporal stores, scheduled or not), whatever
-    # the block size or the schedule's rate, and to nothing else.
+    # Each committed headline counter line applies to launches that run the
+    # same kernel code (chunks, non-temporal stores, scheduled or not),
+    # whatever the block size or the schedule's rate, and to nothing else.
     b = _bench_module()
-    line = [l for l in open(os.path.join(ROOT, "profiles", "gen_kernel_u64_2p26x256.md"))
-            if l.startswith("machine:")][0]
-    kv = dict(tok.split("=", 1) for tok in line.split()[1:])
-    blk, ch, nt, pace = (int(x) for x in kv["launch"].split(","))
-    same = {"block": blk, "chunks": ch, "nontemporal": bool(nt), "pace_gbs": pace}
-    t = b.counter_traffic(same)
+    lines = [l for l in open(os.path.join(ROOT, "profiles", "gen_kernel_u64_2p26x256.md"))
+             if l.startswith("machine:")]
+    assert lines
     alg = 8 * (1 << 26) * 256 + 16 * (1 << 26)
-    assert t is not None and abs(t / alg - 1) < 1e-3
-    assert b.counter_traffic(dict(same, block=1024 if blk != 1024 else 256)) == t
-    if pace:
-        assert b.counter_traffic(dict(same, pace_gbs=pace + 250)) == t
-    assert b.counter_traffic(dict(same, pace_gbs=0 if pace else 7000)) is None
-    assert b.counter_traffic(dict(same, nontemporal=not nt)) is None
-    assert b.counter_traffic(dict(same, chunks=4 if ch != 4 else 1)) is None
+    keys = set()
+    for line in lines:
+        kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+        blk, ch, nt, pace = (int(x) for x in kv["launch"].split(","))
+        same = {"block": blk, "chunks": ch, "nontemporal": bool(nt), "pace_gbs": pace}
+        keys.add(b.launch_key(same))
+        t = b.counter_traffic(same)
+        assert t == int(kv["traffic_bytes_per_launch"]) and abs(t / alg - 1) < 1e-3
+        assert b.counter_traffic(dict(same, block=1024 if blk != 1024 else 256)) == t
+        if pace:
+            assert b.counter_traffic(dict(same, pace_gbs=pace + 250)) == t
+    for ch in (1, 2, 4):
+        for nt in (False, True):
+            for pace in (0, 7000):
+                cfg = {"block": 512, "chunks": ch, "nontemporal": nt, "pace_gbs": pace}
+                if b.launch_key(cfg) not in keys:
+                    assert b.counter_traffic(cfg) is None
