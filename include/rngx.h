@@ -324,15 +324,15 @@ int rngx_generate_batch_noalloc(const rngx_req *reqs, uint32_t m, uint64_t *out,
                                 void *stream);
 
 /* Launch configuration of the batched kernel.
- * values_per_lane: S, values each lane produces per work item (16, 32, 64,
- *   128, 256, 512 or 1024); a work item is a tile of 64 * S output values.
+ * values_per_lane: S, values each lane produces per work item (8, 16, 32,
+ *   64, 128, 256, 512 or 1024); a work item is a tile of 64 * S output values.
  * waves_per_block: 1..4; blocks: 1..65536 (the persistent grid; 0 means 8
  *   waves per compute unit);
  * use_graph: 1 to capture the table upload and the launch in a HIP graph
  *   once and replay it, 0 to launch directly;
  * row_values: values each lane stages in LDS per round before the wave
  *   writes them out (8: 64-byte rows, 5 KiB of LDS per wave; 16: 128-byte
- *   rows, 9 KiB per wave);
+ *   rows, 9 KiB per wave; at most values_per_lane);
  * run_items: 0..64, most work items a wave takes at once (0 means 1;
  *   fewer near the end of the batch, down to 1); within a run, a wave
  *   moving to the next tile of the same request carries each lane's state
@@ -340,6 +340,23 @@ int rngx_generate_batch_noalloc(const rngx_req *reqs, uint32_t m, uint64_t *out,
  * per_item: 1 to launch one wave per work item instead (the grid is sized
  *   to the items, there is no work counter, blocks and run_items are
  *   ignored), 0 for the persistent grid.
+ * group: 0, or the grouped scheduled order with groups of 16, 32, 64 or 128
+ *   wavefronts (per_item must be 0; blocks and run_items are ignored). The
+ *   grid is every block that fits on the device at once, rounded down to
+ *   whole groups; the work items are cut into regions of group *
+ *   group_steps consecutive items, group q takes regions q, q + Q, ... (Q
+ *   groups), and at step s of a region its wavefront j takes item
+ *   s * group + j, so a group's wavefronts write side by side and move
+ *   through the region together; between steps of one request each lane
+ *   carries its state group * 64 * S - S values on with one nibble-table
+ *   product instead of a jump from the stream's start. Stores are
+ *   non-temporal.
+ * group_steps: 1..256 with a group (0 without).
+ * pace_gbs: with a group, 0 or a row schedule of 1000..20000 GB/s: every
+ *   wavefront takes its step k no earlier than its start time + k times the
+ *   time the grid's items of one step take at pace_gbs, on the device's
+ *   constant-rate clock (bounded waits, as for rngx_launch.pace_gbs). 0
+ *   without a group.
  * The output never depends on the configuration. */
 typedef struct rngx_batch_cfg {
     uint32_t values_per_lane;
@@ -349,6 +366,9 @@ typedef struct rngx_batch_cfg {
     uint32_t row_values;
     uint32_t run_items;
     uint32_t per_item;
+    uint32_t group;
+    uint32_t group_steps;
+    uint32_t pace_gbs;
 } rngx_batch_cfg;
 
 int rngx_set_batch_cfg(const rngx_batch_cfg *cfg);
@@ -372,7 +392,10 @@ typedef struct rngx_tune_result {
  * time every candidate configuration of the persistent launch
  * (values_per_lane 64..512 x waves_per_block 2 or 4 x run_items 1 or 8 x
  * 8, 16 or 32 waves per compute unit, those whose LDS fits; 16-value rows)
- * on this request table with HIP events, check
+ * and of the grouped order (values_per_lane 16, 16-value rows, 4
+ * wavefronts per block x groups of 16 or 32 wavefronts x 8 or 16 steps x
+ * pace_gbs 5750, 6000, 6250, 6500 or 6750), each as back-to-back
+ * launches, on this request table with HIP events, check
  * that every candidate's output has the same checksum, keep the fastest as
  * the batch configuration, and report all of them. `out` receives the
  * requests' output. reps: timed launches per candidate (>= 1).

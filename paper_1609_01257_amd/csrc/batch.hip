@@ -189,7 +189,7 @@ __device__ __forceinline__ ItemReq load_req(g_req *__restrict__ reqs, uint32_t j
 // previous tile of the same request), then S values per lane through LDS
 // rows and out with whole-line stores. Returns whether the tile was full,
 // in which case each lane's state ends S values past its start.
-template <int S, int R, bool STAR>
+template <int S, int R, bool STAR, bool NT = false>
 __device__ __forceinline__ bool process_item(const ItemReq &r, uint64_t item, bool carry,
                                              uint64_t &x, uint64_t *lds,
                                              const uint64_t *carry_tab,
@@ -290,7 +290,10 @@ __device__ __forceinline__ bool process_item(const ItemReq &r, uint64_t item, bo
             for (uint32_t i = 0; i < CPR; ++i) {
                 const uint32_t row = RPI * i + lane / CPR;
                 const uint32_t off = row * (uint32_t)S + rd * (uint32_t)ROUND + 2u * ch;
-                *(g_u64x2 *)(tile + off) = v[i];
+                if (NT)
+                    __builtin_nontemporal_store(v[i], (g_u64x2 *)(tile + off));
+                else
+                    *(g_u64x2 *)(tile + off) = v[i];
             }
         } else {
 #pragma unroll
@@ -401,6 +404,85 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
     }
 }
 
+// Wait (bounded) until the device's constant-rate clock reaches `due`: at
+// most about 2^16 polls of about 100 ns, so a wait ends whatever the clock
+// does. Uniform across the wavefront (a scalar clock read).
+__device__ __forceinline__ void wait_clock(uint64_t due)
+{
+    uint32_t polls = 0;
+    while (__builtin_amdgcn_s_memrealtime() < due && ++polls < (1u << 16))
+        __builtin_amdgcn_s_sleep(2);
+}
+
+// The grouped order (rngx_batch_cfg.group). The grid's wavefronts form
+// groups of `group`; the work items are cut into regions of group * steps
+// consecutive items, group q takes regions q, q + Q, ... (Q groups), and at
+// step s of a region its wavefront j takes item s * group + j. A group's
+// wavefronts thus write neighbouring tiles and move through the region
+// together: at any time the grid writes a few dense windows instead of one
+// scattered tile per wavefront. Within a request a wavefront's next item is
+// `group` tiles on, so each lane carries its state group * C - S values on
+// with one nibble-table product (`group_nib`, in LDS); it jumps from the
+// stream's start only at a region's or a request's first item. With
+// delta256 != 0 every wavefront takes its step k no earlier than its start
+// time + k * delta256 / 256 clock ticks.
+template <int S, int R, bool STAR>
+__global__ __launch_bounds__(256) void batch_group_kernel(const BatchDesc *__restrict__ desc,
+                                                          const uint64_t *__restrict__ pow2,
+                                                          const uint64_t *__restrict__ spread,
+                                                          const uint64_t *__restrict__ group_nib,
+                                                          uint32_t group, uint32_t steps,
+                                                          uint64_t delta256)
+{
+    constexpr int LDS_ROW = lds_row(R);
+    extern __shared__ uint64_t lds_dyn[];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint64_t *stride_tab = lds_dyn + (size_t)(blockDim.x >> 6) * 64 * LDS_ROW;
+    uint64_t *lds = lds_dyn + (size_t)wid * 64 * LDS_ROW;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kCarryTable; i += blockDim.x)
+        stride_tab[i] = group_nib[i];
+    __syncthreads();
+
+    const uint64_t n_items = desc->n_items;
+    const uint32_t m = desc->m;
+    g_req *__restrict__ reqs = (g_req *)desc->reqs;
+    g_cu64 *__restrict__ states = (g_cu64 *)desc->states;
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wid;
+    const uint64_t n_groups = (uint64_t)gridDim.x * (blockDim.x >> 6) / group;
+    const uint64_t q = wave / group, j = wave % group;
+    if (q >= n_groups)
+        return;
+    const uint64_t per_region = (uint64_t)group * steps;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    uint64_t sched = 0, x = 0, req_end = 0;
+    uint32_t lo = 0;
+    for (uint64_t reg = q; reg * per_region < n_items; reg += n_groups) {
+        bool carry = false;
+        for (uint32_t st = 0; st < steps; ++st) {
+            const uint64_t item = uniform64(reg * per_region + (uint64_t)st * group + j);
+            if (item >= n_items)
+                break; // the rest of the region lies further on
+            if (delta256) {
+                wait_clock(t0 + (sched >> 8));
+                sched += delta256;
+            }
+            if (!carry) {
+                lo = __builtin_amdgcn_readfirstlane(bisect_request(reqs, m, item));
+                req_end = uniform64(lo + 1 < m ? (uint64_t)reqs[lo + 1].item_begin : n_items);
+            }
+            const ItemReq r = load_req(reqs, lo);
+            const bool full = process_item<S, R, STAR, true>(r, item, carry, x, lds, stride_tab,
+                                                             pow2, spread, states, lane);
+            // Lane l holds the state at T0 + l*S + S when the tile was full;
+            // the wave's next item is `group` tiles on if it is still in
+            // this request.
+            carry = __builtin_amdgcn_readfirstlane(
+                        (uint32_t)(full && item + group < req_end)) != 0;
+        }
+    }
+}
+
 // A batch of at most kSmallReqs requests with its table in the kernel's
 // arguments: one wave per work item, no table upload before the launch.
 template <int S, int R, bool STAR>
@@ -438,12 +520,30 @@ __global__ __launch_bounds__(256) void batch_small_kernel(const SmallTable t,
                                    (g_cu64 *)t.desc.states, lane);
 }
 
+template <int S, int R, bool STAR>
+hipError_t launch_group_t(const BatchDesc *desc, const BatchTables &t, const rngx_batch_cfg &c,
+                          size_t lds_bytes, hipStream_t s)
+{
+    uint64_t delta256 = 0;
+    if (c.pace_gbs) {
+        // One step: every wavefront of the grid writes one tile.
+        const double step_bytes = (double)c.blocks * c.waves_per_block * 64.0 * S * 8.0;
+        delta256 = (uint64_t)(step_bytes / (c.pace_gbs * 1e9) * t.clock_khz * 1e3 * 256.0);
+    }
+    batch_group_kernel<S, R, STAR><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
+        desc, t.pow2, t.spread, t.group_nib, c.group, c.group_steps, delta256);
+    return hipGetLastError();
+}
+
 template <int S, bool STAR>
 hipError_t launch_batch_s(const BatchDesc *desc, const BatchTables &t, const rngx_batch_cfg &c,
                           hipStream_t s)
 {
     const size_t lds_bytes =
         (kCarryTable + (size_t)c.waves_per_block * 64 * lds_row(c.row_values)) * sizeof(uint64_t);
+    if (c.group)
+        return c.row_values == 8 ? launch_group_t<S, 8, STAR>(desc, t, c, lds_bytes, s)
+                                 : launch_group_t<S, 16, STAR>(desc, t, c, lds_bytes, s);
     const uint32_t run = c.run_items ? c.run_items : 1;
     if (c.row_values == 8)
         batch_kernel<S, 8, STAR><<<dim3(c.blocks), dim3(64 * c.waves_per_block), lds_bytes, s>>>(
@@ -497,13 +597,35 @@ hipError_t launch_checksum(const uint64_t *data, uint64_t n, uint64_t *acc, hipS
 
 bool batch_cfg_valid(const rngx_batch_cfg &c)
 {
-    const bool s_ok = c.values_per_lane == 16 || c.values_per_lane == 32 ||
-                      c.values_per_lane == 64 || c.values_per_lane == 128 ||
-                      c.values_per_lane == 256 || c.values_per_lane == 512 ||
-                      c.values_per_lane == 1024;
-    return s_ok && c.waves_per_block >= 1 && c.waves_per_block <= MAX_WAVES_PER_BLOCK &&
-           c.blocks <= 65536 && c.use_graph <= 1 && (c.row_values == 8 || c.row_values == 16) &&
-           c.run_items <= 64 && c.per_item <= 1;
+    const bool s_ok = c.values_per_lane == 8 || c.values_per_lane == 16 ||
+                      c.values_per_lane == 32 || c.values_per_lane == 64 ||
+                      c.values_per_lane == 128 || c.values_per_lane == 256 ||
+                      c.values_per_lane == 512 || c.values_per_lane == 1024;
+    const bool base = s_ok && c.waves_per_block >= 1 &&
+                      c.waves_per_block <= MAX_WAVES_PER_BLOCK && c.blocks <= 65536 &&
+                      c.use_graph <= 1 && (c.row_values == 8 || c.row_values == 16) &&
+                      c.row_values <= c.values_per_lane && c.run_items <= 64 && c.per_item <= 1;
+    if (!base)
+        return false;
+    if (c.group == 0)
+        return c.group_steps == 0 && c.pace_gbs == 0;
+    return batch_group_index(c.group) >= 0 && c.group % c.waves_per_block == 0 &&
+           c.group_steps >= 1 && c.group_steps <= 256 && c.per_item == 0 &&
+           (c.pace_gbs == 0 || (c.pace_gbs >= 1000 && c.pace_gbs <= 20000));
+}
+
+hipError_t batch_group_occupancy(const rngx_batch_cfg &c, int *blocks_per_cu)
+{
+    const size_t lds_bytes =
+        (kCarryTable + (size_t)c.waves_per_block * 64 * lds_row(c.row_values)) * sizeof(uint64_t);
+    const int threads = (int)(64 * c.waves_per_block);
+    // Every S and star variant shares the resource use of its row width
+    // closely enough for the grid size; the S = 16 kernels stand for all.
+    return c.row_values == 8
+               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                     blocks_per_cu, batch_group_kernel<16, 8, false>, threads, lds_bytes)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                     blocks_per_cu, batch_group_kernel<16, 16, false>, threads, lds_bytes);
 }
 
 template <bool STAR>
@@ -511,6 +633,7 @@ hipError_t launch_batch_star(const rngx_batch_cfg &cfg, const BatchDesc *desc,
                              const BatchTables &t, hipStream_t s)
 {
     switch (cfg.values_per_lane) {
+    case 8: return launch_batch_s<8, STAR>(desc, t, cfg, s);
     case 16: return launch_batch_s<16, STAR>(desc, t, cfg, s);
     case 32: return launch_batch_s<32, STAR>(desc, t, cfg, s);
     case 64: return launch_batch_s<64, STAR>(desc, t, cfg, s);
@@ -526,6 +649,7 @@ hipError_t launch_batch_small_star(const rngx_batch_cfg &cfg, const SmallTable &
                                    const BatchTables &t, hipStream_t s)
 {
     switch (cfg.values_per_lane) {
+    case 8: return launch_batch_small_s<8, STAR>(tab, t, cfg, s);
     case 16: return launch_batch_small_s<16, STAR>(tab, t, cfg, s);
     case 32: return launch_batch_small_s<32, STAR>(tab, t, cfg, s);
     case 64: return launch_batch_small_s<64, STAR>(tab, t, cfg, s);

@@ -169,6 +169,10 @@ struct BatchSlot {
 bool batch_cfg_valid(const rngx_batch_cfg &c);
 // Index of an allowed values-per-lane S in the per-S tables.
 int batch_s_index(uint32_t s);
+// Index of an allowed group size of the grouped order, or -1.
+int batch_group_index(uint32_t g);
+// Blocks of the grouped kernel that fit on one compute unit at once.
+hipError_t batch_group_occupancy(const rngx_batch_cfg &c, int *blocks_per_cu);
 // Entries of the per-S carry table: 16 nibble positions x 16 values.
 constexpr int kCarryTable = 256;
 // Entries of the per-S lane-spread table: 16 nibble positions x 16 values x
@@ -179,11 +183,20 @@ struct BatchTables {
     const uint64_t *pow2;       // T^(2^b), b < 64: 64 rows each
     const uint64_t *spread;     // T^(m S) (v << 4q) at ((16 q + v) * 64 + m)
     const uint64_t *carry_nib; // T^(63 S) (next tile, same lane) as kCarryTable nibble entries
+    const uint64_t *group_nib; // grouped order: T^(g 64 S - S) (tile g on), or null
+    uint32_t clock_khz;        // rate of the constant-rate clock
 };
 // Device copies of the jump tables for the current device (thread-safe).
 int batch_tables_locked(const uint64_t **pow2, const uint64_t **spread_all, int *n_cus,
-                        const uint64_t **carry_nib_all = nullptr);
-rngx_batch_cfg resolved_cfg(const rngx_batch_cfg &c, int n_cus);
+                        const uint64_t **carry_nib_all = nullptr,
+                        const uint64_t **group_nib_all = nullptr, int *clock_khz = nullptr);
+// The configuration a launch runs: blocks 0 resolved (8 waves per compute
+// unit), or for the grouped order every block that fits, in whole groups.
+int resolve_batch_cfg(const rngx_batch_cfg &c, int n_cus, rngx_batch_cfg *out);
+// The tables of one launch's S (and group size) among the per-device ones.
+void fill_batch_tables(BatchTables &t, const rngx_batch_cfg &cfg, const uint64_t *pow2,
+                       const uint64_t *spread_all, const uint64_t *nib_all,
+                       const uint64_t *group_all, int clock_khz);
 // Argument checks of a batched call; *total_out = the values requested.
 int batch_validate(const rngx_req *reqs, uint32_t m, const uint64_t *out, uint64_t out_cap,
                    uint64_t *total_out);

@@ -96,7 +96,7 @@ struct Server {
     uint64_t max_pending = 1u << 20;
     uint32_t max_inflight = 2;
     bool star = false; // the output scrambler, fixed at start
-    rngx_batch_cfg cfg{256, 4, 0, 0, 16, 1, 0};
+    rngx_batch_cfg cfg{256, 4, 0, 0, 16, 1, 0, 0, 0, 0};
     std::thread worker;
     int worker_rc = RNGX_OK;
     std::string worker_msg;
@@ -656,7 +656,7 @@ extern "C" int rngx_serve_start(uint64_t seed, uint32_t n_states, void *pool, ui
     // Batch sizes vary: launch directly (no graph) with a grid fitted to the
     // items, 4 waves per block, 8 waves per CU at most; S and the schedule
     // are chosen per batch.
-    s.cfg = rngx_batch_cfg{256, 4, 0, 0, 16, 1, 0};
+    s.cfg = rngx_batch_cfg{256, 4, 0, 0, 16, 1, 0, 0, 0, 0};
     s.star = current_scrambler() == RNGX_SCRAMBLE_STAR;
     s.worker_rc = RNGX_OK;
     s.worker_msg.clear();

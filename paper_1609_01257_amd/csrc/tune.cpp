@@ -39,15 +39,24 @@ int device_signature(std::string *sig)
 
 struct CacheLine {
     std::string device, kind, tuned_on;
-    uint32_t v[7] = {0, 0, 0, 0, 0, 0, 0};
+    uint32_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     double ms = 0.0;
 };
 
 const char *const kPlainKeys[4] = {"block", "chunks", "nontemporal", "pace_gbs"};
-const char *const kBatchKeys[7] = {"values_per_lane", "waves_per_block", "blocks", "use_graph",
-                                   "row_values", "run_items", "per_item"};
+const char *const kBatchKeys[10] = {"values_per_lane", "waves_per_block", "blocks",
+                                    "use_graph",       "row_values",      "run_items",
+                                    "per_item",        "group",           "group_steps",
+                                    "pace_gbs"};
 
-int n_keys(const std::string &kind) { return kind == "batch" ? 7 : 4; }
+int n_keys(const std::string &kind) { return kind == "batch" ? 10 : 4; }
+
+// Keys that lines written before they existed lack: absent means 0 (no
+// schedule, no grouped order).
+bool optional_key(const std::string &kind, int i)
+{
+    return kind == "batch" ? i >= 7 : i == 3;
+}
 const char *const *keys_of(const std::string &kind)
 {
     return kind == "batch" ? kBatchKeys : kPlainKeys;
@@ -97,10 +106,8 @@ bool parse_line(const std::string &line, CacheLine *c)
     const char *const *keys = keys_of(c->kind);
     for (int i = 0; i < n_keys(c->kind); ++i) {
         double v = 0.0;
-        // Lines written before plain launches had a schedule have no
-        // pace_gbs: no schedule.
         if (!get_number(line, keys[i], &v)) {
-            if (std::strcmp(keys[i], "pace_gbs") != 0)
+            if (!optional_key(c->kind, i))
                 return false;
             v = 0.0;
         }
@@ -202,8 +209,10 @@ int tune_cache_record_batch(const rngx_batch_cfg &cfg, double ms, uint32_t m, ui
     if (rc)
         return rc;
     c.kind = "batch";
-    const uint32_t v[7] = {cfg.values_per_lane, cfg.waves_per_block, cfg.blocks, cfg.use_graph,
-                           cfg.row_values,      cfg.run_items,       cfg.per_item};
+    const uint32_t v[10] = {cfg.values_per_lane, cfg.waves_per_block, cfg.blocks,
+                            cfg.use_graph,       cfg.row_values,      cfg.run_items,
+                            cfg.per_item,        cfg.group,           cfg.group_steps,
+                            cfg.pace_gbs};
     std::memcpy(c.v, v, sizeof v);
     c.ms = ms;
     char buf[96];
@@ -247,7 +256,8 @@ extern "C" int rngx_tune_cache_load(const char *path, uint32_t *applied)
         if (c.device != sig)
             continue;
         if (c.kind == "batch") {
-            const rngx_batch_cfg b{c.v[0], c.v[1], c.v[2], c.v[3], c.v[4], c.v[5], c.v[6]};
+            const rngx_batch_cfg b{c.v[0], c.v[1], c.v[2], c.v[3], c.v[4],
+                                   c.v[5], c.v[6], c.v[7], c.v[8], c.v[9]};
             rc = rngx_set_batch_cfg(&b);
         } else {
             const rngx_launch l{c.v[0], c.v[1], c.v[2], c.v[3]};
@@ -291,8 +301,9 @@ extern "C" int rngx_tune_cache_save(const char *path)
     if (rc)
         return rc;
     c.kind = "batch";
-    const uint32_t v[7] = {b.values_per_lane, b.waves_per_block, b.blocks, b.use_graph,
-                           b.row_values,      b.run_items,       b.per_item};
+    const uint32_t v[10] = {b.values_per_lane, b.waves_per_block, b.blocks, b.use_graph,
+                            b.row_values,      b.run_items,       b.per_item, b.group,
+                            b.group_steps,     b.pace_gbs};
     std::memcpy(c.v, v, sizeof v);
     return merge_into_cache(path, c);
 }

@@ -45,7 +45,8 @@ class BatchCfg(ctypes.Structure):
     _fields_ = [("values_per_lane", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
                 ("blocks", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
                 ("row_values", ctypes.c_uint32), ("run_items", ctypes.c_uint32),
-                ("per_item", ctypes.c_uint32)]
+                ("per_item", ctypes.c_uint32), ("group", ctypes.c_uint32),
+                ("group_steps", ctypes.c_uint32), ("pace_gbs", ctypes.c_uint32)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -407,9 +408,12 @@ def generate_batch_noalloc(reqs, out, stream=None):
 
 
 def set_batch_cfg(values_per_lane=256, waves_per_block=4, blocks=0, use_graph=True,
-                  row_values=16, run_items=1, per_item=False):
+                  row_values=16, run_items=1, per_item=False, group=0, group_steps=0,
+                  pace_gbs=0):
+    """Batch launch configuration; group > 0 selects the grouped order (groups of
+    `group` wavefronts, `group_steps` steps per region, optional row schedule)."""
     cfg = BatchCfg(values_per_lane, waves_per_block, blocks, int(bool(use_graph)), row_values,
-                   run_items, int(bool(per_item)))
+                   run_items, int(bool(per_item)), group, group_steps, pace_gbs)
     _check(lib().rngx_set_batch_cfg(ctypes.byref(cfg)))
 
 
@@ -422,7 +426,8 @@ def get_batch_cfg():
 def _cfg_dict(c):
     return {"values_per_lane": c.values_per_lane, "waves_per_block": c.waves_per_block,
             "blocks": c.blocks, "use_graph": bool(c.use_graph), "row_values": c.row_values,
-            "run_items": c.run_items, "per_item": bool(c.per_item)}
+            "run_items": c.run_items, "per_item": bool(c.per_item), "group": c.group,
+            "group_steps": c.group_steps, "pace_gbs": c.pace_gbs}
 
 
 def autotune_batch(reqs, out, reps=2, stream=None):

@@ -223,12 +223,29 @@ def test_batch_argument_errors_without_gpu():
     assert "2^64 - 1" in rngx.last_error()
     for bad in [(100, 4, 0, 1, 16, 1, 0), (256, 5, 0, 1, 16, 1, 0), (256, 4, 70000, 1, 16, 1, 0),
                 (256, 4, 0, 2, 16, 1, 0), (256, 4, 0, 1, 12, 1, 0), (256, 4, 0, 1, 16, 65, 0),
-                (256, 4, 0, 1, 16, 1, 2)]:
+                (256, 4, 0, 1, 16, 1, 2),
+                (8, 4, 0, 1, 16, 0, 0),                   # rows wider than S
+                (256, 4, 0, 1, 16, 1, 0, 0, 16, 0),       # steps without a group
+                (256, 4, 0, 1, 16, 1, 0, 0, 0, 7000),     # a schedule without a group
+                (256, 4, 0, 1, 16, 1, 0, 48, 16, 0),      # not a group size
+                (256, 3, 0, 1, 16, 1, 0, 64, 16, 0),      # group not whole blocks
+                (256, 4, 0, 1, 16, 1, 0, 64, 0, 0),       # no steps
+                (256, 4, 0, 1, 16, 1, 0, 64, 257, 0),
+                (256, 4, 0, 1, 16, 1, 1, 64, 16, 0),      # one wave per item
+                (256, 4, 0, 1, 16, 1, 0, 64, 16, 999),
+                (256, 4, 0, 1, 16, 1, 0, 64, 16, 20001)]:
         assert L.rngx_set_batch_cfg(ctypes.byref(rngx.BatchCfg(*bad))) == rngx.RNGX_E_INVAL, bad
+    assert "group_steps" in rngx.last_error()
     rngx.set_batch_cfg(512, 2, 100, False, 8, 3)
     assert rngx.get_batch_cfg() == {"values_per_lane": 512, "waves_per_block": 2, "blocks": 100,
                                     "use_graph": False, "row_values": 8, "run_items": 3,
-                                    "per_item": False}
+                                    "per_item": False, "group": 0, "group_steps": 0,
+                                    "pace_gbs": 0}
+    rngx.set_batch_cfg(8, 2, 0, True, 8, 0, False, 128, 256, 20000)
+    assert rngx.get_batch_cfg() == {"values_per_lane": 8, "waves_per_block": 2, "blocks": 0,
+                                    "use_graph": True, "row_values": 8, "run_items": 0,
+                                    "per_item": False, "group": 128, "group_steps": 256,
+                                    "pace_gbs": 20000}
     rngx.set_batch_cfg(64, 4, 0, True, 16, 1, True)
     assert rngx.get_batch_cfg()["per_item"] is True
     rngx.set_batch_cfg()
@@ -270,6 +287,16 @@ def test_tune_cache_errors_without_gpu(tmp_path):
         f.write_text(good + "\n" + bad + "\n")
         assert L.rngx_tune_cache_load(str(f).encode(), None) == rngx.RNGX_E_INVAL, bad
         assert "line 2" in rngx.last_error()
+    # Batch lines written before the grouped order (no group keys) still
+    # parse; a negative group does not.
+    old_batch = ('{"device": "gfx950 256cu", "kind": "batch", "values_per_lane": 256, '
+                 '"waves_per_block": 4, "blocks": 0, "use_graph": 1, "row_values": 16, '
+                 '"run_items": 1, "per_item": 0, "ms": 1.000000, "tuned_on": "m=1 values=1"}')
+    f = tmp_path / "b.jsonl"
+    f.write_text(old_batch + "\n" + old_batch.replace('"per_item": 0', '"per_item": 0, "group": -1')
+                 + "\n")
+    assert L.rngx_tune_cache_load(str(f).encode(), None) == rngx.RNGX_E_INVAL
+    assert "line 2" in rngx.last_error()
     # The plain autotuner needs an initialised generator.
     res = rngx.PlainTuneResult()
     assert L.rngx_autotune_plain(4, 0, 16, 1, None, ctypes.byref(res)) == rngx.RNGX_E_NOINIT

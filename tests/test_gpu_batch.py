@@ -63,6 +63,42 @@ def test_every_per_item_config(oracle, S, wpb, graph, row):
     assert np.array_equal(_run(_reqs(r), r.total), exp)
 
 
+# The grouped order: groups of wavefronts moving through regions of
+# consecutive tiles together, carrying state `group` tiles on within a
+# request; 1 and 5 steps per region put most items at region edges, 16
+# steps carry most of them; the 5-step cases also run a slow schedule.
+@pytest.mark.parametrize("S,wpb,graph,group,steps", list(itertools.product(
+    [8, 16, 64], [1, 4], [False, True], [16, 64, 128], [1, 5, 16])))
+def test_every_group_config(oracle, S, wpb, graph, group, steps):
+    r = inputs.ragged_requests(m=23, seed=97, max_len=400000, max_offset=5000)
+    exp = oracle.generate_batch(_oracle_reqs(oracle, r))
+    rngx.set_batch_cfg(S, wpb, 0, graph, 8 if S == 8 else 16, 0, False, group, steps,
+                       2000 if steps == 5 else 0)
+    assert np.array_equal(_run(_reqs(r), r.total), exp)
+
+
+@pytest.mark.parametrize("entry", ["generate_batch", "generate_batch_noalloc"])
+@pytest.mark.parametrize("star", [False, True])
+def test_group_order_long_streams_and_scrambler(oracle, entry, star):
+    # Requests of up to 2^21 values (many carried steps per wavefront), the
+    # scheduled grouped order the autotuner tries, both entry points.
+    r = inputs.ragged_requests(m=40, seed=5, max_len=1 << 21, max_offset=10**9)
+    exp = oracle.generate_batch(_oracle_reqs(oracle, r))
+    if star:
+        exp = oracle.scramble_array(exp)
+    rngx.set_batch_cfg(8, 4, 0, entry == "generate_batch", 8, 0, False, 32, 16, 7000)
+    rngx.set_scrambler(rngx.SCRAMBLE_STAR if star else rngx.SCRAMBLE_NONE)
+    try:
+        out = torch.zeros(r.total + 9, dtype=torch.int64, device="cuda")
+        getattr(rngx, entry)(_reqs(r), out[2:2 + r.total])
+        torch.cuda.synchronize()
+    finally:
+        rngx.set_scrambler(rngx.SCRAMBLE_NONE)
+    host = out.cpu().numpy().view(np.uint64)
+    assert not host[:2].any() and not host[2 + r.total:].any()
+    assert np.array_equal(host[2:2 + r.total], exp)
+
+
 @pytest.mark.parametrize("m", [1, 2, 7, 15, 16, 17])
 @pytest.mark.parametrize("S", [16, 64, 256])
 def test_small_tables_in_kernel_arguments(oracle, m, S):
@@ -191,8 +227,12 @@ def test_autotune_agrees_across_candidates(oracle):
     r = inputs.ragged_requests(m=64, seed=8, max_len=300000)
     out = torch.zeros(r.total, dtype=torch.int64, device="cuda")
     res = rngx.autotune_batch(_reqs(r), out, reps=1)
-    assert len(res["tried"]) >= 32 and res["best_ms"] > 0
-    assert {c["run_items"] for c, _ in res["tried"]} == {1, 8}
+    assert len(res["tried"]) == 52 and res["best_ms"] > 0
+    assert {c["run_items"] for c, _ in res["tried"][:32]} == {1, 8}
+    grouped = [c for c, _ in res["tried"][32:]]
+    assert {(c["values_per_lane"], c["group"], c["group_steps"]) for c in grouped} == {
+        (16, g, k) for g in (16, 32) for k in (8, 16)}
+    assert {c["pace_gbs"] for c in grouped} == {5750, 6000, 6250, 6500, 6750}
     assert {c["per_item"] for c, _ in res["tried"]} == {False}
     assert rngx.get_batch_cfg() == res["best"]
     torch.cuda.synchronize()

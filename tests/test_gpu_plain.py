@@ -433,7 +433,7 @@ def test_tune_cache_roundtrip(tmp_path):
     try:
         rngx.set_launch(False, 1024, 2, True, 6250)
         rngx.set_launch(True, 256, 1, False)
-        rngx.set_batch_cfg(128, 2, 77, False, 16, 8, False)
+        rngx.set_batch_cfg(16, 4, 0, False, 16, 0, False, 64, 16, 7000)
         rngx.tune_cache_save(path)
         # An entry of another device is kept on save and ignored on load.
         other = ('{"device": "gfx000 1cu", "kind": "plain_u64", "block": 64, "chunks": 1, '
@@ -447,9 +447,10 @@ def test_tune_cache_roundtrip(tmp_path):
                                           "pace_gbs": 6250}
         assert rngx.get_launch(True) == {"block": 256, "chunks": 1, "nontemporal": False,
                                          "pace_gbs": 0}
-        assert rngx.get_batch_cfg() == {"values_per_lane": 128, "waves_per_block": 2,
-                                        "blocks": 77, "use_graph": False, "row_values": 16,
-                                        "run_items": 8, "per_item": False}
+        assert rngx.get_batch_cfg() == {"values_per_lane": 16, "waves_per_block": 4,
+                                        "blocks": 0, "use_graph": False, "row_values": 16,
+                                        "run_items": 0, "per_item": False, "group": 64,
+                                        "group_steps": 16, "pace_gbs": 7000}
         rngx.tune_cache_save(path)
         lines = path.read_text().splitlines()
         # Kept, in the current form (a line without pace_gbs has no schedule).
