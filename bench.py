@@ -29,6 +29,11 @@ GIB = 1 << 30
 # pace_gbs); u32 block 0 = chosen by size.
 LIB_DEFAULT_U64 = (512, 4, 0, 0)
 LIB_DEFAULT_U32 = (0, 0, 0, 0)
+# The request server's launch configuration for batches above 2^23 values
+# (the grouped order), used by the in-pool batched comparator.
+SERVER_LARGE_BATCH_CFG = dict(values_per_lane=16, waves_per_block=4, blocks=0, use_graph=False,
+                              row_values=16, run_items=0, per_item=False, group=32,
+                              group_steps=8, pace_gbs=6250)
 
 
 def log(*a):
@@ -332,8 +337,8 @@ def serving(torch, rngx, seconds, plain_gbs):
         rngx.serve_stop()
         # The same requests, in consecutive batches of the server's mean
         # batch size, each written by the batched kernel into the pool in the
-        # schedule the server uses for large batches (persistent grid,
-        # S = 256). Its rate over the kernels' own durations (HIP events on
+        # schedule the server uses for large batches (the grouped order,
+        # SERVER_LARGE_BATCH_CFG). Its rate over the kernels' own durations (HIP events on
         # their stream) is what the server would reach with no overhead of
         # its own: the ratio isolates the server from kernel speed and from
         # where the pool lies in HBM.
@@ -356,7 +361,7 @@ def serving(torch, rngx, seconds, plain_gbs):
             places.append(words[off:off + size])
             off += (size + 31) & ~31     # 256-byte aligned, as the server's pool ring places them
         tuned = rngx.get_batch_cfg()
-        rngx.set_batch_cfg(256, 4, 0, False, 16, 1, False)
+        rngx.set_batch_cfg(**SERVER_LARGE_BATCH_CFG)
         try:
             rngx.generate_batch(chunks[0], places[0])      # warm-up
             torch.cuda.synchronize()

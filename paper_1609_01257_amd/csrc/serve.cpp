@@ -179,14 +179,24 @@ constexpr uint64_t kSmallBatchValues = 1u << 23;
 // batches are latency-bound: one wave per 1,024-value item (S = 16) spreads
 // a request over the most waves, each storing soonest (Poisson runs at
 // 2k/10k/50k req/s: p50 23/23/28 us against 28/27/33 with 4,096-value
-// items). Larger ones run on the persistent grid with S = 256, which
-// measured fastest when batches overlap on the device (backlog of 243 GB:
-// 5.45-5.51 TB/s against 4.90-4.97 for one wave per item).
+// items). Larger ones run in the grouped order (S = 16, groups of 32
+// wavefronts, 8 steps per region, schedule 6,250 GB/s: the batch
+// autotuner's pick on the 4,096-stream table), which served a 243 GB
+// backlog at 5.85 TB/s (median of three) against 5.52 for the persistent
+// grid with S = 256 and 3.18 with the schedule halved for two batches in
+// flight; the persistent grid had measured 5.45-5.51 against 4.90-4.97
+// for one wave per item.
 void serve_schedule(uint64_t values, rngx_batch_cfg &cfg)
 {
     const bool small = values <= kSmallBatchValues;
-    cfg.values_per_lane = small ? 16u : 256u;
+    cfg.values_per_lane = 16;
+    cfg.waves_per_block = 4;
+    cfg.row_values = 16;
     cfg.per_item = small ? 1u : 0u;
+    cfg.run_items = small ? 1u : 0u;
+    cfg.group = small ? 0u : 32u;
+    cfg.group_steps = small ? 0u : 8u;
+    cfg.pace_gbs = small ? 0u : 6250u;
 }
 
 // Whether the next batch (the first max_batch admitted requests, padded as
