@@ -408,7 +408,8 @@ int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *out, uint64_
  * every configuration block {256, 512, 1024} x chunks {1, 2, 4} x
  * nontemporal {0, 1} (18 bases), then row schedules (pace_gbs): every
  * base at 6000, 6750 and 7500 GB/s, and the two bases fastest with a
- * schedule at 5500..8000 GB/s in steps of 250 (88 candidates in all), on
+ * schedule at 5500..8000 GB/s in steps of 250 (88 candidates in all),
+ * then the four fastest again with three times the launches, on
  * the current generator (its n_states) for n_iters
  * iterations on `stream`, with HIP events around each candidate's timed
  * launches; every candidate starts from a snapshot of the states, so all
@@ -428,13 +429,18 @@ typedef struct rngx_plain_tune_entry {
     rngx_launch cfg;
     double ms; /* mean kernel time over the timed launches */
 } rngx_plain_tune_entry;
+#define RNGX_TUNE_CONFIRM 4
 typedef struct rngx_plain_tune_result {
     rngx_launch best;
-    double best_ms;
+    double best_ms;  /* the best confirmation timing */
     double best_gbs; /* algorithmic bytes (output + 16 per state) / best_ms */
     uint32_t n_tried;
     uint32_t reserved;
     rngx_plain_tune_entry tried[RNGX_TUNE_MAX];
+    /* The RNGX_TUNE_CONFIRM fastest candidates timed again with 3 * reps
+     * launches each (fewer if fewer were tried; unused entries zero); best
+     * is the fastest of these. */
+    rngx_plain_tune_entry confirm[RNGX_TUNE_CONFIRM];
 } rngx_plain_tune_result;
 int rngx_autotune_plain(uint32_t n_iters, int u32, void *out, uint32_t reps, void *stream,
                         rngx_plain_tune_result *result);

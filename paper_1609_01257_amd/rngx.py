@@ -71,7 +71,7 @@ class PlainTuneEntry(ctypes.Structure):
 class PlainTuneResult(ctypes.Structure):
     _fields_ = [("best", Launch), ("best_ms", ctypes.c_double), ("best_gbs", ctypes.c_double),
                 ("n_tried", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("tried", PlainTuneEntry * 128)]
+                ("tried", PlainTuneEntry * 128), ("confirm", PlainTuneEntry * 4)]
 
 
 class ServeReport(ctypes.Structure):
@@ -459,7 +459,9 @@ def autotune_plain(n_iters, out, reps=2, u32=False, stream=None):
                                      ctypes.byref(res)))
     k = min(res.n_tried, 128)
     return {"best": _launch_dict(res.best), "best_ms": res.best_ms, "best_gbs": res.best_gbs,
-            "tried": [(_launch_dict(res.tried[i].cfg), res.tried[i].ms) for i in range(k)]}
+            "tried": [(_launch_dict(res.tried[i].cfg), res.tried[i].ms) for i in range(k)],
+            "confirm": [(_launch_dict(res.confirm[i].cfg), res.confirm[i].ms)
+                        for i in range(4) if res.confirm[i].cfg.block]}
 
 
 def tune_cache_save(path):

@@ -407,7 +407,12 @@ def test_plain_autotuner_keeps_state_and_output(oracle, u32, n):
         fine_paces = [5500, 5750, 6250, 6500, 7000, 7250, 7750, 8000]
         assert [c["pace_gbs"] for c, _ in fine] == fine_paces * 2
         assert [{**c, "pace_gbs": 0} for c, _ in fine[::8]] == [bases[i] for i in top]
-        assert res["best"] == min(tried, key=lambda t: t[1])[0]
+        # Confirmation: the four fastest again; the fastest of those wins.
+        top4 = sorted(tried, key=lambda t: t[1])[:4]
+        assert [c for c, _ in res["confirm"]] == [c for c, _ in top4]
+        assert all(ms > 0 for _, ms in res["confirm"])
+        assert res["best"] == min(res["confirm"], key=lambda t: t[1])[0]
+        assert res["best_ms"] == min(ms for _, ms in res["confirm"])
         assert rngx.get_launch(u32) == res["best"]
         assert rngx.info()[2] == 3
         exp = oracle.generate(seed, n, 3 + 2 * iters)
