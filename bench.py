@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 GIB = 1 << 30
 # The library's default plain launches (block, chunks, non-temporal,
 # pace_gbs); u32 block 0 = chosen by size.
-LIB_DEFAULT_U64 = (512, 4, 0, 0)
+LIB_DEFAULT_U64 = (512, 2, 1, 7000)
 LIB_DEFAULT_U32 = (0, 0, 0, 0)
 # The request server's launch configuration for batches above 2^23 values
 # (the grouped order), used by the in-pool batched comparator.

@@ -195,12 +195,11 @@ int generate_locked(Generator &c, uint32_t n_iters, void *out, hipStream_t s, bo
     const int tok = prof::begin("RNG_KERNEL", s);
     rngx_launch cfg = u32 ? c.cfg32 : c.cfg64;
     if (cfg.block == 0) {
-        // The library's choice by size (u32 launches measured on MI355X:
-        // more work-items per lane pays below 2^26 states, fewer lanes
-        // per block up to 2^20).
-        cfg.block = c.n <= (1u << 20) ? 256 : 512;
-        cfg.chunks = c.n < (1u << 26) ? 4 : (u32 ? 2 : 4);
-        cfg.nontemporal = 0;
+        // The library's choice: the row-scheduled launch at 7,000 GB/s,
+        // 6.8-7.1 TB/s at every size from 2^20 to 2^26 states x 256
+        // iterations, u64 and u32, on MI355X (unscheduled: 5.4-6.5), with
+        // a margin below the rates where a schedule falls behind.
+        cfg = rngx_launch{512, 2, 1, 7000};
     }
     take_stray_error("before the rng kernel launch");
     hipError_t e = launch_gen(cfg, u32,

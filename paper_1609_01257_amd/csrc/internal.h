@@ -277,8 +277,8 @@ struct Generator {
     uint64_t *state = nullptr;       // n states, library-owned device memory
     hipStream_t lib_stream = nullptr; // the init kernel's stream
     hipEvent_t state_ready = nullptr; // last use of `state` (any stream)
-    rngx_launch cfg64{512, 4, 0, 0}; // fastest measured at 2^26 x 256 on MI355X
-    rngx_launch cfg32{0, 0, 0, 0};   // chosen per call by n (auto_launch_u32)
+    rngx_launch cfg64{512, 2, 1, 7000}; // row-scheduled; see rngx_launch in rngx.h
+    rngx_launch cfg32{0, 0, 0, 0};      // block 0: the library's choice (generate_locked)
     // Streams and events of the device-to-host pipeline (pipeline.cpp).
     hipStream_t pipe_gen = nullptr, pipe_copy = nullptr;
     hipEvent_t copy_done[2] = {nullptr, nullptr};

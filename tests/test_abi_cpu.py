@@ -102,14 +102,18 @@ def test_set_launch_validation():
         cfg = rngx.Launch(*bad)
         assert rngx.lib().rngx_set_launch(0, ctypes.byref(cfg)) == rngx.RNGX_E_INVAL
     assert "pace_gbs" in rngx.last_error()
+    # The library's defaults: the scheduled launch for u64, its own choice
+    # (block 0) for u32.
+    default = rngx.get_launch(False)
+    assert default == {"block": 512, "chunks": 2, "nontemporal": True, "pace_gbs": 7000}
     rngx.set_launch(False, 512, 4, True)
     assert rngx.get_launch(False) == {"block": 512, "chunks": 4, "nontemporal": True,
                                       "pace_gbs": 0}
     rngx.set_launch(False, 256, 2, False, 6500)
     assert rngx.get_launch(False) == {"block": 256, "chunks": 2, "nontemporal": False,
                                       "pace_gbs": 6500}
-    rngx.set_launch(False, 512, 4, False)
-    # u32 defaults to the library's choice by size (block 0); it can be set
+    rngx.set_launch(False, **default)
+    # u32 defaults to the library's choice (block 0); it can be set
     # explicitly and back.
     assert rngx.get_launch(True)["block"] == 0
     rngx.set_launch(True, 256, 1, False)

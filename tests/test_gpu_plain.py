@@ -71,15 +71,23 @@ def test_zero_iterations_is_noop(oracle):
 @pytest.mark.parametrize("u32", [False, True])
 @pytest.mark.parametrize("n", [1000, (1 << 20) + 3, (1 << 22) + 6])
 def test_automatic_launch_choice(oracle, u32, n):
-    # block 0: the library picks the configuration by n; same output.
+    # block 0: the library's choice (the scheduled launch on aligned rows,
+    # the unscheduled kernel on shifted ones); same output.
     default = rngx.get_launch(u32)
     try:
         rngx.set_launch(u32, 0, 0, False)
-        got = run(8, n, 2, u32=u32, offset=1)
         exp = (oracle.generate_u32 if u32 else oracle.generate)(8, n, 2)
-        assert np.array_equal(got, exp)
+        for offset in (0, 1):
+            assert np.array_equal(run(8, n, 2, u32=u32, offset=offset), exp), offset
     finally:
         rngx.set_launch(u32, **default)
+
+
+def test_library_defaults():
+    rngx.init(1, 64)
+    assert rngx.get_launch(False) == {"block": 512, "chunks": 2, "nontemporal": True,
+                                      "pace_gbs": 7000}
+    assert rngx.get_launch(True)["block"] == 0
 
 
 @pytest.mark.parametrize("u32", [False, True])
