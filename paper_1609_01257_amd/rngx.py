@@ -411,7 +411,9 @@ def set_batch_cfg(values_per_lane=256, waves_per_block=4, blocks=0, use_graph=Tr
                   row_values=16, run_items=1, per_item=False, group=0, group_steps=0,
                   pace_gbs=0):
     """Batch launch configuration; group > 0 selects the grouped order (groups of
-    `group` wavefronts, `group_steps` steps per region, optional row schedule)."""
+    `group` wavefronts, `group_steps` steps per region, optional row schedule).
+    The arguments default to the persistent grid with S = 256; the library's
+    own default configuration (before any call) is the grouped order."""
     cfg = BatchCfg(values_per_lane, waves_per_block, blocks, int(bool(use_graph)), row_values,
                    run_items, int(bool(per_item)), group, group_steps, pace_gbs)
     _check(lib().rngx_set_batch_cfg(ctypes.byref(cfg)))

@@ -225,6 +225,12 @@ def test_batch_argument_errors_without_gpu():
     late = rngx.make_reqs([1], [0], [2**64 - 5], [6])
     assert L.rngx_generate_batch(late.ctypes.data, 1, 16, 6, None) == rngx.RNGX_E_INVAL
     assert "2^64 - 1" in rngx.last_error()
+    # The library's default: the grouped order.
+    assert rngx.get_batch_cfg() == {"values_per_lane": 16, "waves_per_block": 4, "blocks": 0,
+                                    "use_graph": True, "row_values": 16, "run_items": 0,
+                                    "per_item": False, "group": 32, "group_steps": 8,
+                                    "pace_gbs": 6250}
+    default_batch = rngx.get_batch_cfg()
     for bad in [(100, 4, 0, 1, 16, 1, 0), (256, 5, 0, 1, 16, 1, 0), (256, 4, 70000, 1, 16, 1, 0),
                 (256, 4, 0, 2, 16, 1, 0), (256, 4, 0, 1, 12, 1, 0), (256, 4, 0, 1, 16, 65, 0),
                 (256, 4, 0, 1, 16, 1, 2),
@@ -252,7 +258,7 @@ def test_batch_argument_errors_without_gpu():
                                     "pace_gbs": 20000}
     rngx.set_batch_cfg(64, 4, 0, True, 16, 1, True)
     assert rngx.get_batch_cfg()["per_item"] is True
-    rngx.set_batch_cfg()
+    rngx.set_batch_cfg(**default_batch)
 
 
 def test_noalloc_batch_argument_errors_without_gpu():
