@@ -219,6 +219,25 @@ def test_inflight_cap_keeps_results(oracle, server, max_inflight):
     assert st["completed"] == len(hist) and st["batches"] >= len(hist) // 32
 
 
+@pytest.mark.parametrize("max_inflight", [1, 2])
+def test_large_batches_in_the_grouped_order(oracle, server, max_inflight):
+    # Batches above 2^23 values run in the grouped order: requests of
+    # 2^20..2^22 values, 8 to a batch, on 16 streams (cursors continue).
+    seed, n_states = 3141, 16
+    rngx.serve_set_max_inflight(max_inflight)
+    pool = server(seed, n_states, 2 << 30, 4, 8)
+    rng = np.random.default_rng(max_inflight)
+    hist = [(int(g), int(L)) for g, L in zip(rng.integers(0, n_states, 40),
+                                              rng.integers(1 << 20, 1 << 22, 40))]
+    tickets = rngx.serve_submit_many([g for g, _ in hist], [L for _, L in hist])
+    exp = oracle.serve_expected(seed, hist)
+    for t, (g, L), e in zip(tickets, hist, exp):
+        assert np.array_equal(_values(pool, rngx.serve_wait(int(t), 60.0), L), e), (g, L)
+        rngx.serve_release(int(t))
+    st = rngx.serve_stats()
+    assert st["completed"] == len(hist) and st["batches"] < len(hist)
+
+
 def test_scrambled_server_matches_oracle(oracle, server):
     # A server started with the scrambler on serves scrambled words; the
     # cursor rule is unchanged.
@@ -228,7 +247,7 @@ def test_scrambled_server_matches_oracle(oracle, server):
         pool = server(seed, 300, 256 << 20)
     finally:
         rngx.set_scrambler(rngx.SCRAMBLE_NONE)
-    hist = _history(11, 150, 300, 40000) + [(7, 3000000)]   # one batch above 2^20 values
+    hist = _history(11, 150, 300, 40000) + [(7, 9000000)]   # one batch above 2^23 values
     tickets = [rngx.serve_submit(g, L) for g, L in hist]
     exp = oracle.serve_expected(seed, hist)
     for t, (g, L), e in zip(tickets, hist, exp):
