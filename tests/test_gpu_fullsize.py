@@ -109,7 +109,7 @@ def batched_table(oracle):
 
 
 @pytest.mark.parametrize("schedule", ["bench-default", "autotuned", "persistent-S256",
-                                      "per-item-S128"])
+                                      "per-item-S128", "grouped-S16", "grouped-S8-unscheduled"])
 def test_batched_table_full(batched_table, schedule):
     r, reqs, oreqs, bases = batched_table
     _say("batched 4096-stream table, %s" % schedule)
@@ -124,6 +124,10 @@ def test_batched_table_full(batched_table, schedule):
             rngx.set_batch_cfg(256, 4, 0, True, 16, 1, False)
         elif schedule == "per-item-S128":
             rngx.set_batch_cfg(128, 4, 0, True, 16, 1, True)
+        elif schedule == "grouped-S16":               # the library's default
+            rngx.set_batch_cfg(16, 4, 0, True, 16, 0, False, 32, 8, 6250)
+        elif schedule == "grouped-S8-unscheduled":
+            rngx.set_batch_cfg(8, 2, 0, False, 8, 0, False, 128, 3, 0)
         out.fill_(0)
         rngx.generate_batch(reqs, out)
         res = parity.compare_requests_device(out, oreqs, bases)
