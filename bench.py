@@ -654,25 +654,34 @@ def main():
         # output) into three buffers from separate allocations: the write
         # rate of the row-ordered store stream depends on where a buffer
         # landed in HBM, reproducibly per buffer.
+        # Each buffer is timed with the unscheduled launch (block 512, 2
+        # chunks, normal stores) and with the library's default (scheduled).
         n, iters = 1 << 26, 256
         rngx.init(1, n)
         bufs = [torch.empty(n * iters, dtype=torch.int32, device="cuda") for _ in range(3)]
         res = []
         st = torch.cuda.current_stream()
+        launches = {"unscheduled 512,2,0,0": (512, 2, 0, 0), "default": LIB_DEFAULT_U32}
         for i, buf in enumerate(bufs):
-            rngx.generate_u32(iters, buf)
-            torch.cuda.synchronize()
-            rates = []
-            for _ in range(3):
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
-                a.record(st)
+            entry = {"buffer": i}
+            for name, cfg in launches.items():
+                rngx.set_launch(True, *cfg)
                 rngx.generate_u32(iters, buf)
-                b.record(st)
-                b.synchronize()
-                rates.append(round(n * iters * 4 / (a.elapsed_time(b) * 1e-3) / 1e9, 1))
-            log("placement probe: buffer %d at 0x%x: %s GB/s" % (i, buf.data_ptr(), rates))
-            res.append({"buffer": i, "kernel_gbs": rates})
+                torch.cuda.synchronize()
+                rates = []
+                for _ in range(3):
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(st)
+                    rngx.generate_u32(iters, buf)
+                    b.record(st)
+                    b.synchronize()
+                    rates.append(round(n * iters * 4 / (a.elapsed_time(b) * 1e-3) / 1e9, 1))
+                log("placement probe: buffer %d at 0x%x, %s: %s GB/s" % (i, buf.data_ptr(), name,
+                                                                         rates))
+                entry[name] = rates
+            res.append(entry)
+        rngx.set_launch(True, *LIB_DEFAULT_U32)
         rngx.shutdown()
         print(json.dumps({"placement_probe": res}), flush=True)
         return
