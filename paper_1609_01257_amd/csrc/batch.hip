@@ -404,6 +404,49 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchDesc *__restrict_
     }
 }
 
+// A full tile at virtual index T0 of a request whose output index 0 is at
+// obase[vbase]: lane l holds the state at T0 + l*S; S values per lane
+// through LDS rows, whole-line stores. Same stores as process_item's full
+// path.
+template <int S, int R, bool STAR, bool NT>
+__device__ __forceinline__ void emit_full_tile(uint64_t &x, uint64_t *lds, g_u64 *__restrict__ tile,
+                                               uint32_t lane)
+{
+    constexpr int ROUND = R;
+    constexpr int LDS_ROW = lds_row(R);
+    constexpr uint32_t CPR = R / 2;
+    constexpr uint32_t RPI = 64 / CPR;
+    for (uint32_t rd = 0; rd < (uint32_t)S / ROUND; ++rd) {
+#pragma unroll
+        for (int s = 0; s < ROUND; ++s) {
+            lds[lane * LDS_ROW + s] = out_word<STAR>(x);
+            x = xs_step(x);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t ch = lane % CPR;
+        u64x2 v[CPR];
+#pragma unroll
+        for (uint32_t i = 0; i < CPR; ++i) {
+            const uint32_t row = RPI * i + lane / CPR;
+            v[i] = *reinterpret_cast<const u64x2 *>(&lds[row * LDS_ROW + 2u * ch]);
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < CPR; ++i) {
+            const uint32_t row = RPI * i + lane / CPR;
+            const uint32_t off = row * (uint32_t)S + rd * (uint32_t)ROUND + 2u * ch;
+            if (NT)
+                __builtin_nontemporal_store(v[i], (g_u64x2 *)(tile + off));
+            else
+                *(g_u64x2 *)(tile + off) = v[i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // Wait (bounded) until the device's constant-rate clock reaches `due`: at
 // most about 2^16 polls of about 100 ns, so a wait ends whatever the clock
 // does. Uniform across the wavefront (a scalar clock read).
@@ -455,8 +498,13 @@ __global__ __launch_bounds__(256) void batch_group_kernel(const BatchDesc *__res
         return;
     const uint64_t per_region = (uint64_t)group * steps;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    constexpr uint64_t C = 64ull * S;
     uint64_t sched = 0, x = 0, req_end = 0;
     uint32_t lo = 0;
+    // The current request while carrying: its last tile start T0, its end
+    // E (virtual indices) and its output base address (output of virtual
+    // index P at obase + P).
+    uint64_t cur_T0 = 0, cur_E = 0, cur_obase = 0;
     for (uint64_t reg = q; reg * per_region < n_items; reg += n_groups) {
         bool carry = false;
         for (uint32_t st = 0; st < steps; ++st) {
@@ -467,11 +515,24 @@ __global__ __launch_bounds__(256) void batch_group_kernel(const BatchDesc *__res
                 wait_clock(t0 + (sched >> 8));
                 sched += delta256;
             }
+            if (carry && cur_T0 + (uint64_t)group * C + C <= cur_E) {
+                // A full tile `group` tiles on in the same request.
+                cur_T0 = uniform64(cur_T0 + (uint64_t)group * C);
+                x = lane_carry(stride_tab, x);
+                emit_full_tile<S, R, STAR, true>(
+                    x, lds, reinterpret_cast<g_u64 *>(cur_obase) + cur_T0, lane);
+                carry = __builtin_amdgcn_readfirstlane(
+                            (uint32_t)(item + group < req_end)) != 0;
+                continue;
+            }
             if (!carry) {
                 lo = __builtin_amdgcn_readfirstlane(bisect_request(reqs, m, item));
                 req_end = uniform64(lo + 1 < m ? (uint64_t)reqs[lo + 1].item_begin : n_items);
             }
             const ItemReq r = load_req(reqs, lo);
+            cur_T0 = uniform64((r.first_tile + (item - r.item_begin)) * C);
+            cur_E = uniform64(r.vbase + r.length);
+            cur_obase = uniform64(reinterpret_cast<uintptr_t>(r.dst) - r.vbase * sizeof(uint64_t));
             const bool full = process_item<S, R, STAR, true>(r, item, carry, x, lds, stride_tab,
                                                              pow2, spread, states, lane);
             // Lane l holds the state at T0 + l*S + S when the tile was full;
