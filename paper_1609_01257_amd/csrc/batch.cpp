@@ -46,7 +46,7 @@ int batch_group_index(uint32_t g)
 }
 
 // The constant tables every batch launch reads, in static device memory: one
-// copy per device, which lives as long as the process (942 KiB). They are
+// copy per device, which lives as long as the process (1,136 KiB). They are
 // filled on a device's first batched call of any kind, so later calls, also
 // the allocation-free entry point, only enqueue work.
 __device__ __align__(256) uint64_t g_pow2[64 * 64];                  // T^(2^b), 64 rows each
