@@ -386,13 +386,17 @@ typedef struct rngx_tune_entry {
     rngx_batch_cfg cfg;
     double ms; /* mean kernel time over the timed repetitions */
 } rngx_tune_entry;
+#define RNGX_TUNE_CONFIRM 4
 typedef struct rngx_tune_result {
     rngx_batch_cfg best;
-    double best_ms;
+    double best_ms;  /* the best confirmation timing */
     double best_gbs; /* output bytes / best_ms */
     uint32_t n_tried;
     uint32_t reserved;
     rngx_tune_entry tried[RNGX_TUNE_MAX];
+    /* The RNGX_TUNE_CONFIRM fastest candidates timed again with 3 * reps
+     * launches each; best is the fastest of these. */
+    rngx_tune_entry confirm[RNGX_TUNE_CONFIRM];
 } rngx_tune_result;
 
 /* Autotuner (the paper's work-size suggestion, Section 6.1, made empirical):
@@ -402,7 +406,8 @@ typedef struct rngx_tune_result {
  * and of the grouped order (values_per_lane 16, 16-value rows, 4
  * wavefronts per block x groups of 16 or 32 wavefronts x 8 or 16 steps x
  * pace_gbs 5750, 6000, 6250, 6500 or 6750), each as back-to-back
- * launches, on this request table with HIP events, check
+ * launches, then the four fastest again with three times the launches,
+ * on this request table with HIP events, check
  * that every candidate's output has the same checksum, keep the fastest as
  * the batch configuration, and report all of them. `out` receives the
  * requests' output. reps: timed launches per candidate (>= 1).
@@ -436,7 +441,6 @@ typedef struct rngx_plain_tune_entry {
     rngx_launch cfg;
     double ms; /* mean kernel time over the timed launches */
 } rngx_plain_tune_entry;
-#define RNGX_TUNE_CONFIRM 4
 typedef struct rngx_plain_tune_result {
     rngx_launch best;
     double best_ms;  /* the best confirmation timing */

@@ -56,7 +56,7 @@ class TuneEntry(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("best", BatchCfg), ("best_ms", ctypes.c_double), ("best_gbs", ctypes.c_double),
                 ("n_tried", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("tried", TuneEntry * 128)]
+                ("tried", TuneEntry * 128), ("confirm", TuneEntry * 4)]
 
 
 class Launch(ctypes.Structure):
@@ -442,7 +442,9 @@ def autotune_batch(reqs, out, reps=2, stream=None):
                                      stream_handle(stream), ctypes.byref(res)))
     n = min(res.n_tried, 128)
     return {"best": _cfg_dict(res.best), "best_ms": res.best_ms, "best_gbs": res.best_gbs,
-            "tried": [(_cfg_dict(res.tried[i].cfg), res.tried[i].ms) for i in range(n)]}
+            "tried": [(_cfg_dict(res.tried[i].cfg), res.tried[i].ms) for i in range(n)],
+            "confirm": [(_cfg_dict(res.confirm[i].cfg), res.confirm[i].ms)
+                        for i in range(4) if res.confirm[i].cfg.values_per_lane]}
 
 
 def _launch_dict(c):

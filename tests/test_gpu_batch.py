@@ -233,6 +233,11 @@ def test_autotune_agrees_across_candidates(oracle):
     assert {(c["values_per_lane"], c["group"], c["group_steps"]) for c in grouped} == {
         (16, g, k) for g in (16, 32) for k in (8, 16)}
     assert {c["pace_gbs"] for c in grouped} == {5750, 6000, 6250, 6500, 6750}
+    # Confirmation: the four fastest again; the fastest of those wins.
+    top4 = sorted(res["tried"], key=lambda t: t[1])[:4]
+    assert [c for c, _ in res["confirm"]] == [c for c, _ in top4]
+    assert res["best"] == min(res["confirm"], key=lambda t: t[1])[0]
+    assert res["best_ms"] == min(ms for _, ms in res["confirm"])
     assert {c["per_item"] for c, _ in res["tried"]} == {False}
     assert rngx.get_batch_cfg() == res["best"]
     torch.cuda.synchronize()
