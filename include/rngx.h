@@ -405,7 +405,7 @@ typedef struct rngx_tune_result {
  * 8, 16 or 32 waves per compute unit, those whose LDS fits; 16-value rows)
  * and of the grouped order (values_per_lane 16, 16-value rows, 4
  * wavefronts per block x groups of 16 or 32 wavefronts x 8 or 16 steps x
- * pace_gbs 5750, 6000, 6250, 6500 or 6750), each as back-to-back
+ * pace_gbs 5750, 6000, 6125, 6250, 6375, 6500 or 6750), each as back-to-back
  * launches, then the four fastest again with three times the launches,
  * on this request table with HIP events, check
  * that every candidate's output has the same checksum, keep the fastest as

@@ -889,10 +889,10 @@ extern "C" int rngx_autotune_batch(const rngx_req *reqs, uint32_t m, uint64_t *o
     // 6,000-6,500 GB/s; faster schedules fall behind and lose the order).
     const uint32_t groups[2] = {16, 32};
     const uint32_t gsteps[2] = {8, 16};
-    const uint32_t paces[5] = {5750, 6000, 6250, 6500, 6750};
+    const uint32_t paces[7] = {5750, 6000, 6125, 6250, 6375, 6500, 6750};
     for (uint32_t gi = 0; gi < 2; ++gi) {
         for (uint32_t ki = 0; ki < 2; ++ki) {
-            for (uint32_t pi = 0; pi < 5; ++pi) {
+            for (uint32_t pi = 0; pi < 7; ++pi) {
                 rngx_batch_cfg c{};
                 c.values_per_lane = 16;
                 c.waves_per_block = 4;
